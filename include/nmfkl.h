@@ -1,0 +1,150 @@
+/*
+ * nmfkl.h -- C ABI of the MI355X (gfx950) library for nonnegative matrix factorisation with
+ * KL divergence by randomized coordinate descent (Nguyen & Ho, arXiv 1604.04026).
+ *
+ * Problem (Section 1, eq. 1): V (n x m, nonnegative, sparse) ~ W^T F with W (r x n) and
+ * F (r x m) nonnegative, minimising D(V || W^T F) plus the optional L1/L2 terms of eq. 2.
+ * Alg. 1 alternates two independent families of subproblems (eq. 3): one per column of V
+ * (update F with W fixed) and one per row of V (update W with F fixed); each is solved by
+ * Alg. 2, a pass of projected Newton steps over the r coordinates in a random order shared
+ * by every column and row of the outer iteration, with first and second derivatives
+ * (eq. 6) reduced over the nonzeros of the column/row plus precomputed factor sums.
+ *
+ * Conventions
+ *  - Every function returns an int status: NMFKL_OK (0) or a negative NMFKL_E_* code.  No
+ *    C++ exception and no abort crosses the ABI.  nmfkl_last_error() gives a message.
+ *  - Arguments are validated before any state changes; on error the handle is unchanged.
+ *  - Layout: V is given twice, as CSC (columns = the m instances) and CSR (rows = the n
+ *    features), with int64 pointers, int32 indices strictly increasing inside each
+ *    column/row, and float32 values (finite, >= 0).  Both factors are stored point-major,
+ *    row-major float32: W as n x r (row i = the r-vector of feature i, i.e. the paper's W
+ *    transposed) and F as m x r (row j = instance j, the paper's F transposed).
+ *  - Pointers marked (device) are device memory owned by the caller; they must stay valid
+ *    until the handle is destroyed.  The library allocates only its own scratch and frees
+ *    it in the matching destroy call.  Host pointers are read during the call only.
+ *  - All device work is enqueued on the caller's HIP stream (passed as void*; NULL means
+ *    the default stream).  Only functions that return host values synchronise that stream.
+ *    Device-side failures surface at the next synchronising call.
+ *  - Precision: values, factors and all per-nonzero arithmetic are float32; the factor
+ *    column sums and the objective are accumulated in float64.
+ *  - A handle is not thread-safe: calls on one handle must not overlap.
+ */
+#ifndef NMFKL_H
+#define NMFKL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NMFKL_OK 0
+#define NMFKL_E_INVAL (-1)       /* invalid argument or malformed input (nothing changed) */
+#define NMFKL_E_NOMEM (-2)       /* device or host allocation failed / admission refused */
+#define NMFKL_E_DEVICE (-3)      /* HIP runtime error or device-side failure */
+#define NMFKL_E_NONFINITE (-4)   /* a factor holds a NaN/Inf (detected at a synchronising call) */
+#define NMFKL_E_BUSY (-5)        /* no free slot (serving) */
+#define NMFKL_E_UNSUPPORTED (-6) /* valid request outside this build's limits */
+
+#define NMFKL_R_MAX 128          /* largest supported rank r */
+
+/* Method parameters.  Fill with nmfkl_params_default() and override fields. */
+typedef struct nmfkl_params {
+    double alpha_W;  /* eq. 2 alpha_1: L2 weight on W (default 0) */
+    double alpha_F;  /* eq. 2 alpha_2: L2 weight on F (default 0) */
+    double beta_W;   /* eq. 2 beta_1: L1 weight on W (default 0) */
+    double beta_F;   /* eq. 2 beta_2: L1 weight on F (default 0) */
+    double eps_log;  /* smoothing added to the model inside log and denominators, Alg. 2 output line (1e-10) */
+    double eps_g;    /* relative gradient threshold of Alg. 2's while-test (1e-5) */
+    double eps_x;    /* step-size break ratio of Alg. 2, Section 3 value 0.1 */
+    int32_t t_max;   /* Newton steps per coordinate (16) */
+    int32_t j_max;   /* halvings of a decreasing step rejected by the descent guard (8) */
+    int32_t literal_break; /* 1: break test on the signed step as printed (ablation), 0: on |step| */
+    int32_t guard;   /* 1: descent guard on decreasing steps (default), 0: plain projected Newton */
+    uint64_t seed;   /* Philox key of the coordinate orders (0) */
+    int32_t foldin_max_passes; /* fold-in: passes at most (200) */
+    double foldin_tol;         /* fold-in: stop when the KL decrease <= tol * KL (1e-5) */
+    int32_t refresh_model;     /* 1: recompute the model at the nonzeros from W and F at the start of
+                                  every nmfkl_sweep_F unless nmfkl_objective just did (default);
+                                  0: carry it from the previous half (identical in exact arithmetic) */
+    int32_t collect_stats;     /* 1: count derivative evaluations / steps / guard events (slower) */
+} nmfkl_params;
+
+typedef struct nmfkl_problem {
+    int32_t n, m, r;           /* V is n x m, rank r (1 <= r <= NMFKL_R_MAX) */
+    int64_t nnz;               /* number of stored entries (same in both copies) */
+    const int64_t* csc_ptr;    /* (device) m+1 */
+    const int32_t* csc_idx;    /* (device) nnz row ids */
+    const float* csc_val;      /* (device) nnz */
+    const int64_t* csr_ptr;    /* (device) n+1 */
+    const int32_t* csr_idx;    /* (device) nnz column ids */
+    const float* csr_val;      /* (device) nnz */
+    float* W;                  /* (device) n x r, in/out */
+    float* F;                  /* (device) m x r, in/out */
+} nmfkl_problem;
+
+typedef struct nmfkl_stats {
+    int64_t coords;    /* coordinate visits */
+    int64_t evals;     /* derivative evaluations (eq. 6 reductions) */
+    int64_t steps;     /* accepted Newton steps */
+    int64_t halvings;  /* descent-guard halvings */
+    int64_t rejects;   /* steps abandoned by the guard */
+    int64_t tmax_hits; /* coordinates stopped by t_max */
+} nmfkl_stats;
+
+typedef struct nmfkl_handle nmfkl_handle;
+typedef struct nmfkl_model nmfkl_model;
+
+/* Defaults listed field by field above. */
+int nmfkl_params_default(nmfkl_params* p);
+
+/* The coordinate order of outer iteration t (Alg. 1: "a randomized ordered set of
+ * {1..r}", here 0-based): a Fisher-Yates shuffle of 0..r-1 driven by Philox-4x64-10 with
+ * key (seed, 0) and counter (b, t, stream, 0), b = 0, 1, ...; word w picks
+ * j = floor(w * (i + 1) / 2^64) for i = r-1 down to 1.  Stream 0 is the sweeps, stream 1
+ * the fold-in passes.  ids: host array of r int32.  Host only, no device work. */
+int nmfkl_permutation(uint64_t seed, uint64_t t, uint64_t stream, int32_t r, int32_t* ids);
+
+/* Create a handle over a problem.  Validates the shapes (host) and then, on the device,
+ * the CSC/CSR structure (pointer monotonicity and ends, index ranges and strict order,
+ * values finite and >= 0, CSR equal to the transpose of CSC) and W, F finite and >= 0;
+ * synchronises the stream once.  Builds the nnz bins, the CSC<->CSR position maps and the
+ * scratch buffers.  Errors: NMFKL_E_INVAL (shape/structure/value), NMFKL_E_NOMEM,
+ * NMFKL_E_DEVICE.  On error *out is NULL. */
+int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_stream,
+                 nmfkl_handle** out);
+
+/* Alg. 1, first half of outer iteration t: sumW = W 1 (float64), then Alg. 2 on every
+ * column j of V with A = W, x = F_j, (alpha_F, beta_F) and the order of iteration t.
+ * Updates F in place.  Asynchronous.  t >= 0. */
+int nmfkl_sweep_F(nmfkl_handle* h, int32_t t);
+
+/* Alg. 1, second half of outer iteration t: sumF = F 1 (float64), then Alg. 2 on every
+ * row i of V with A = F, x = W_i, (alpha_W, beta_W) and the same order.  Updates W in
+ * place.  Asynchronous.  t >= 0. */
+int nmfkl_sweep_W(nmfkl_handle* h, int32_t t);
+
+/* eq. 1, D(V || W^T F) in float64 for the current W, F: the per-nonzero terms
+ * v log(v/M) - v with M = W_i . F_j, plus sum(W^T F) = sumW . sumF.  Synchronises.
+ * +inf if some nonzero has M = 0; NMFKL_E_NONFINITE if a factor holds NaN/Inf. */
+int nmfkl_objective(nmfkl_handle* h, double* D_out);
+
+/* Tell the handle that the caller changed W or F outside the library: the model values
+ * the handle carries between halves are recomputed before the next half-sweep. */
+int nmfkl_invalidate_model(nmfkl_handle* h);
+
+/* Counters accumulated since creation (all zero unless params.collect_stats).
+ * Synchronises. */
+int nmfkl_get_stats(nmfkl_handle* h, nmfkl_stats* out);
+
+/* Free the library's scratch.  Synchronises the stream first. */
+int nmfkl_destroy(nmfkl_handle* h);
+
+/* Message of the last failed call on h (h may be NULL: the last failure of a create). */
+const char* nmfkl_last_error(const nmfkl_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NMFKL_H */

@@ -22,8 +22,9 @@
  *     output line smooths the log; eq. 6 is then the exact derivative of that objective);
  *   - the while-test threshold is relative: enter if g < -eps_g*P, or if g > eps_g*P and
  *     x_k > 0, where P = sumA_k + alpha*x_k + beta is the positive part of g;
- *   - the break test compares the step magnitude: |dx| < eps_x * x_before (eps_x = 0.1,
- *     Section 3); the literal signed test is kept behind literal_break for the ablation;
+ *   - the break test compares the magnitude of Alg. 2's projected Newton step dx (before
+ *     any halving by the guard below): |dx| < eps_x * x_before (eps_x = 0.1, Section 3);
+ *     the literal signed test is kept behind literal_break for the ablation;
  *   - a decreasing step is accepted only if g(x0) + g(x1) >= 0 (else halved up to j_max
  *     times, then abandoned).  Along one coordinate g is concave, so this guarantees that
  *     the subproblem objective does not increase; increasing steps need no guard;
@@ -206,6 +207,7 @@ void orc_coordinate_update(int64_t L, const int32_t* idx, const double* v, const
             double xn = x[k] - g / h;
             d = (xn > 0.0 ? xn : 0.0) - x[k];
         }
+        const double dN = d; /* the projected Newton step of Alg. 2 (before any halving) */
         double gn, hn, Pn;
         trial_model(L, idx, A, r, k, Ax, d, Axn);
         orc_coordinate_derivatives(L, idx, v, A, r, k, Axn, sumA[k], x[k] + d, alpha, beta,
@@ -229,7 +231,7 @@ void orc_coordinate_update(int64_t L, const int32_t* idx, const double* v, const
         g = gn; h = hn; P = Pn;
         ++steps;
         st->steps++;
-        int stop = prm->literal_break ? (d < prm->eps_x * xs) : (fabs(d) < prm->eps_x * xs);
+        int stop = prm->literal_break ? (dN < prm->eps_x * xs) : (fabs(dN) < prm->eps_x * xs);
         if (stop) break;
         if (steps >= prm->t_max) { st->tmax_hits++; break; }
     }

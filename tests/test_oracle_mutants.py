@@ -29,7 +29,7 @@ MUTANTS = {
                                  "(((__uint128_t)w * (uint64_t)(i)) >> 64)"),
     "W-half uses F regulariser": ("ids, prm,\n               st, sumF_out);",
                                   "ids, prm,\n               st, sumF_out); (void)0;"),
-    "break test inverted": ("(fabs(d) < prm->eps_x * xs)", "(fabs(d) > prm->eps_x * xs)"),
+    "break test inverted": ("(fabs(dN) < prm->eps_x * xs)", "(fabs(dN) > prm->eps_x * xs)"),
     "W-half wrong alpha": ("half_sweep(n, csr_ptr, csr_idx, csr_val, m, F, W, r, prm->alpha_W, prm->beta_W,",
                            "half_sweep(n, csr_ptr, csr_idx, csr_val, m, F, W, r, prm->alpha_F, prm->beta_F,"),
 }
