@@ -25,8 +25,9 @@
  *  - All device work is enqueued on the caller's HIP stream (passed as void*; NULL means
  *    the default stream).  Only functions that return host values synchronise that stream.
  *    Device-side failures surface at the next synchronising call.
- *  - Precision: values, factors and all per-nonzero arithmetic are float32; the factor
- *    column sums and the objective are accumulated in float64.
+ *  - Precision: values, factors and the derivative sums are float32; the model values at
+ *    the nonzeros (W_i . F_j, kept between halves), the factor column sums and the
+ *    objective are float64.
  *  - A handle is not thread-safe: calls on one handle must not overlap.
  */
 #ifndef NMFKL_H
@@ -68,6 +69,7 @@ typedef struct nmfkl_params {
                                   every nmfkl_sweep_F unless nmfkl_objective just did (default);
                                   0: carry it from the previous half (identical in exact arithmetic) */
     int32_t collect_stats;     /* 1: count derivative evaluations / steps / guard events (slower) */
+    int32_t collect_timings;   /* 1: bracket every launch group with HIP events (nmfkl_get_timings) */
 } nmfkl_params;
 
 typedef struct nmfkl_problem {
@@ -91,6 +93,30 @@ typedef struct nmfkl_stats {
     int64_t rejects;   /* steps abandoned by the guard */
     int64_t tmax_hits; /* coordinates stopped by t_max */
 } nmfkl_stats;
+
+/* Launch groups timed when params.collect_timings is set. */
+#define NMFKL_T_SUMS_F 0   /* F-half: order, permuted copy of W and its float64 column sums */
+#define NMFKL_T_FUSED_F 1  /* F-half: the binned launch over columns of <= 1024 nonzeros */
+#define NMFKL_T_LONG_F 2   /* F-half: cooperative launches over longer columns */
+#define NMFKL_T_SUMS_W 3   /* W-half: order, permuted copy of F and its column sums */
+#define NMFKL_T_FUSED_W 4  /* W-half: the binned launch over rows of <= 1024 nonzeros */
+#define NMFKL_T_LONG_W 5   /* W-half: cooperative launches over longer rows */
+#define NMFKL_T_MODEL 6    /* model values at the nonzeros (+ eq. 1 terms): refresh / objective */
+#define NMFKL_NUM_TIMED 7
+
+typedef struct nmfkl_kernel_timing {
+    double ms_total;      /* summed HIP-event time of the timed launches */
+    int64_t launches;     /* number of timed launch groups */
+    double gather_bytes;  /* algorithmic bytes of one launch group under the gather model:
+                             per nonzero 4 (index) + 4 (value) + 4r (the fixed factor's row),
+                             per segment 8 (pointer) + 8r (x read and written); for the model
+                             pass per nonzero 4 + 4 + 4r + 8 (model written) + per column 4r */
+    double updates;       /* coordinate updates of one launch group: nonzeros x r */
+} nmfkl_kernel_timing;
+
+typedef struct nmfkl_timings {
+    nmfkl_kernel_timing k[NMFKL_NUM_TIMED];
+} nmfkl_timings;
 
 typedef struct nmfkl_handle nmfkl_handle;
 typedef struct nmfkl_model nmfkl_model;
@@ -136,6 +162,13 @@ int nmfkl_invalidate_model(nmfkl_handle* h);
 /* Counters accumulated since creation (all zero unless params.collect_stats).
  * Synchronises. */
 int nmfkl_get_stats(nmfkl_handle* h, nmfkl_stats* out);
+
+/* Accumulated event times since creation or the last reset (all zero unless
+ * params.collect_timings).  Synchronises. */
+int nmfkl_get_timings(nmfkl_handle* h, nmfkl_timings* out);
+
+/* Zero the accumulated timings.  Synchronises. */
+int nmfkl_reset_timings(nmfkl_handle* h);
 
 /* Free the library's scratch.  Synchronises the stream first. */
 int nmfkl_destroy(nmfkl_handle* h);

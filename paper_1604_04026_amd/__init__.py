@@ -17,8 +17,8 @@ from .build import LIB as _LIB_PATH
 __all__ = [
     "NmfklError", "NmfklParams", "NmfklProblem", "NmfklStats", "load", "nmfkl_params_default",
     "nmfkl_permutation", "nmfkl_create", "nmfkl_sweep_F", "nmfkl_sweep_W", "nmfkl_objective",
-    "nmfkl_invalidate_model", "nmfkl_get_stats", "nmfkl_destroy", "nmfkl_last_error",
-    "DeviceProblem", "upload", "Handle", "EXPORTED_SYMBOLS",
+    "nmfkl_invalidate_model", "nmfkl_get_stats", "nmfkl_get_timings", "nmfkl_reset_timings",
+    "nmfkl_destroy", "nmfkl_last_error", "DeviceProblem", "upload", "Handle", "EXPORTED_SYMBOLS",
 ]
 
 NMFKL_OK = 0
@@ -28,8 +28,8 @@ R_MAX = 128
 
 EXPORTED_SYMBOLS = [
     "nmfkl_params_default", "nmfkl_permutation", "nmfkl_create", "nmfkl_sweep_F", "nmfkl_sweep_W",
-    "nmfkl_objective", "nmfkl_invalidate_model", "nmfkl_get_stats", "nmfkl_destroy",
-    "nmfkl_last_error",
+    "nmfkl_objective", "nmfkl_invalidate_model", "nmfkl_get_stats", "nmfkl_get_timings",
+    "nmfkl_reset_timings", "nmfkl_destroy", "nmfkl_last_error",
 ]
 
 
@@ -50,6 +50,7 @@ class NmfklParams(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("foldin_max_passes", ctypes.c_int32), ("foldin_tol", ctypes.c_double),
         ("refresh_model", ctypes.c_int32), ("collect_stats", ctypes.c_int32),
+        ("collect_timings", ctypes.c_int32),
     ]
 
 
@@ -69,6 +70,22 @@ class NmfklStats(ctypes.Structure):
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+TIMED = ["sums_F", "fused_F", "long_F", "sums_W", "fused_W", "long_W", "model"]
+
+
+class NmfklKernelTiming(ctypes.Structure):
+    _fields_ = [("ms_total", ctypes.c_double), ("launches", ctypes.c_int64),
+                ("gather_bytes", ctypes.c_double), ("updates", ctypes.c_double)]
+
+
+class NmfklTimings(ctypes.Structure):
+    _fields_ = [("k", NmfklKernelTiming * len(TIMED))]
+
+    def as_dict(self):
+        return {name: {f: getattr(self.k[i], f) for f, _ in NmfklKernelTiming._fields_}
+                for i, name in enumerate(TIMED)}
 
 
 _lib = None
@@ -95,6 +112,8 @@ def load(path: str | None = None):
     lib.nmfkl_objective.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     lib.nmfkl_invalidate_model.argtypes = [vp]
     lib.nmfkl_get_stats.argtypes = [vp, ctypes.POINTER(NmfklStats)]
+    lib.nmfkl_get_timings.argtypes = [vp, ctypes.POINTER(NmfklTimings)]
+    lib.nmfkl_reset_timings.argtypes = [vp]
     lib.nmfkl_destroy.argtypes = [vp]
     lib.nmfkl_last_error.argtypes = [vp]
     lib.nmfkl_last_error.restype = ctypes.c_char_p
@@ -229,6 +248,16 @@ def nmfkl_get_stats(h: Handle) -> dict:
     s = NmfklStats()
     _check(load().nmfkl_get_stats(h._ptr, ctypes.byref(s)), h._ptr)
     return s.as_dict()
+
+
+def nmfkl_get_timings(h: Handle) -> dict:
+    t = NmfklTimings()
+    _check(load().nmfkl_get_timings(h._ptr, ctypes.byref(t)), h._ptr)
+    return t.as_dict()
+
+
+def nmfkl_reset_timings(h: Handle):
+    _check(load().nmfkl_reset_timings(h._ptr), h._ptr)
 
 
 def nmfkl_destroy(h: Handle):

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <string>
 #include <vector>
 
 #include "nmfkl_internal.hpp"
@@ -19,10 +20,16 @@ thread_local std::string g_create_error;
 enum ModelState { kModelNone = 0, kModelCscFresh, kModelCsc, kModelCsr };
 
 struct BinPlan {
-    BlockWork* work = nullptr;  // device: family 0 blocks, then family 1 blocks
+    BlockWork* work = nullptr;  // device: blocks of the fused launch
     int32_t* segs = nullptr;    // device
-    int nblocks[2] = {0, 0};    // blocks per kernel family
-    int64_t heavy = 0;          // segments longer than the fused launches handle
+    int nblocks = 0;
+    // long segments: cooperative launches ("rounds"), each within the co-residency capacity
+    LongWork* long_work = nullptr;  // device, all rounds concatenated
+    struct Round { int first, nblocks, ngroups, pmax; };
+    std::vector<Round> rounds;
+    int max_groups = 0, max_pmax = 0;
+    // algorithmic (gather-model) bytes and updates of the fused and of the long launches
+    double fused_bytes = 0, fused_updates = 0, long_bytes = 0, long_updates = 0;
 };
 
 }  // namespace
@@ -49,7 +56,16 @@ struct nmfkl_handle {
     double* dscal = nullptr;      // device scalar (objective total)
     double* host_scal = nullptr;  // pinned host scalar
     unsigned long long* stats = nullptr;
+    double* coop_partials = nullptr;   // cross-block partial sums of long segments
+    unsigned* coop_counters = nullptr; // their arrival counters
+    unsigned* dev_err = nullptr;       // device-side error flags (bounded waits)
+    int long_capacity = 0;             // co-resident long-segment blocks
     BinPlan binF, binW;
+    // timing (params.collect_timings): event pairs per launch group, resolved on demand
+    struct Pending { int kind; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> event_pool;
+    nmfkl_timings timings{};
     int model = kModelNone;
     std::string err;
 };
@@ -79,11 +95,59 @@ hipError_t dalloc(T** p, size_t count) {
     return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
 }
 
+// ---- timing helpers -------------------------------------------------------------------
+hipError_t take_event(nmfkl_handle* h, hipEvent_t* ev) {
+    if (!h->event_pool.empty()) {
+        *ev = h->event_pool.back();
+        h->event_pool.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(ev);
+}
+
+// Starts a timed launch group; returns the index of the pending record or -1 when off.
+int timer_begin(nmfkl_handle* h, int kind) {
+    if (!h->prm.collect_timings) return -1;
+    nmfkl_handle::Pending p{kind, nullptr, nullptr};
+    if (take_event(h, &p.a) != hipSuccess || take_event(h, &p.b) != hipSuccess) return -1;
+    if (hipEventRecord(p.a, h->stream) != hipSuccess) return -1;
+    h->pending.push_back(p);
+    return (int)h->pending.size() - 1;
+}
+
+void timer_end(nmfkl_handle* h, int idx) {
+    if (idx < 0) return;
+    (void)hipEventRecord(h->pending[idx].b, h->stream);
+}
+
+hipError_t resolve_timings(nmfkl_handle* h) {
+    if (h->pending.empty()) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return e;
+    for (auto& p : h->pending) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            h->timings.k[p.kind].ms_total += ms;
+            h->timings.k[p.kind].launches += 1;
+        }
+        h->event_pool.push_back(p.a);
+        h->event_pool.push_back(p.b);
+    }
+    h->pending.clear();
+    return hipSuccess;
+}
+
 void release(nmfkl_handle* h) {
+    for (auto& p : h->pending) { h->event_pool.push_back(p.a); h->event_pool.push_back(p.b); }
+    h->pending.clear();
+    for (hipEvent_t ev : h->event_pool) (void)hipEventDestroy(ev);
+    h->event_pool.clear();
     auto f = [](void* p) { if (p) (void)hipFree(p); };
     f(h->Ap); f(h->sumA); f(h->partials); f(h->ids); f(h->Mcsc); f(h->Mcsr);
     f(h->csc2csr); f(h->csr2csc); f(h->obj_partials); f(h->sums2); f(h->dscal); f(h->stats);
     f(h->binF.work); f(h->binF.segs); f(h->binW.work); f(h->binW.segs);
+    f(h->binF.long_work); f(h->binW.long_work);
+    f(h->coop_partials); f(h->coop_counters); f(h->dev_err);
     if (h->host_scal) (void)hipHostFree(h->host_scal);
 }
 
@@ -94,30 +158,32 @@ int variant_for(int64_t L) {
     return -1;
 }
 
-// Group segments by variant (longest variants first, so that long blocks start early) and
-// cut each group into blocks of kFusedThreads / G segments.
+// Segments up to kMaxFusedLength: grouped by variant (longest variants first, so that long
+// blocks start early) and cut into blocks of kFusedThreads / G segments.  Longer segments:
+// B = ceil(L / kLongCapacity) blocks each, packed longest first into cooperative rounds of at
+// most long_capacity blocks.
 int plan_bins(nmfkl_handle* h, const int64_t* dptr, int64_t Q, BinPlan* plan) {
     std::vector<int64_t> ptr(Q + 1);
     HIP_TRY(h, hipMemcpy(ptr.data(), dptr, (Q + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+    auto len = [&](int32_t q) { return ptr[q + 1] - ptr[q]; };
     std::vector<std::vector<int32_t>> groups(kNumVariants);
-    int64_t heavy = 0;
+    std::vector<int32_t> longs;
     for (int64_t q = 0; q < Q; ++q) {
-        const int v = variant_for(ptr[q + 1] - ptr[q]);
-        if (v < 0) { ++heavy; continue; }
-        groups[v].push_back((int32_t)q);
+        const int v = variant_for(len((int32_t)q));
+        if (v < 0) longs.push_back((int32_t)q);
+        else groups[v].push_back((int32_t)q);
     }
-    plan->heavy = heavy;
+    const double r = h->prob.r;
+    auto seg_bytes = [&](int32_t q) { return (double)len(q) * (8.0 + 4.0 * r) + 8.0 + 8.0 * r; };
+    for (int v = 0; v < kNumVariants; ++v)
+        for (int32_t q : groups[v]) { plan->fused_bytes += seg_bytes(q); plan->fused_updates += (double)len(q) * r; }
+    for (int32_t q : longs) { plan->long_bytes += seg_bytes(q); plan->long_updates += (double)len(q) * r; }
     std::vector<int32_t> segs;
     std::vector<BlockWork> work;
-    int fam_blocks[2] = {0, 0};
     for (int v = kNumVariants - 1; v >= 0; --v) {
-        const int fam = family_of(v);
         const int spb = kFusedThreads / kVariants[v].G;
         auto& g = groups[v];
-        // longest segments first inside a variant too
-        std::stable_sort(g.begin(), g.end(), [&](int32_t a, int32_t b) {
-            return (ptr[a + 1] - ptr[a]) > (ptr[b + 1] - ptr[b]);
-        });
+        std::stable_sort(g.begin(), g.end(), [&](int32_t a, int32_t b) { return len(a) > len(b); });
         for (size_t i = 0; i < g.size(); i += spb) {
             BlockWork w;
             w.variant = v;
@@ -126,23 +192,43 @@ int plan_bins(nmfkl_handle* h, const int64_t* dptr, int64_t Q, BinPlan* plan) {
             w.pad = 0;
             for (int k = 0; k < w.count; ++k) segs.push_back(g[i + k]);
             work.push_back(w);
-            ++fam_blocks[fam];
         }
     }
-    // family 1 variants come first in the loop above; store family 0 first
-    std::vector<BlockWork> ordered;
-    for (int fam = 0; fam < 2; ++fam)
-        for (const BlockWork& w : work)
-            if (family_of(w.variant) == fam) ordered.push_back(w);
-    work.swap(ordered);
-    plan->nblocks[0] = fam_blocks[0];
-    plan->nblocks[1] = fam_blocks[1];
+    plan->nblocks = (int)work.size();
     HIP_TRY(h, dalloc(&plan->work, work.size()));
     HIP_TRY(h, dalloc(&plan->segs, segs.size()));
     if (!work.empty())
         HIP_TRY(h, hipMemcpy(plan->work, work.data(), work.size() * sizeof(BlockWork), hipMemcpyHostToDevice));
     if (!segs.empty())
         HIP_TRY(h, hipMemcpy(plan->segs, segs.data(), segs.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+
+    std::stable_sort(longs.begin(), longs.end(), [&](int32_t a, int32_t b) { return len(a) > len(b); });
+    std::vector<LongWork> lw;
+    BinPlan::Round cur{0, 0, 0, 0};
+    for (int32_t q : longs) {
+        const int B = (int)((len(q) + kLongCapacity - 1) / kLongCapacity);
+        if (B > h->long_capacity)
+            return fail(h, NMFKL_E_UNSUPPORTED,
+                        "a segment of " + std::to_string(len(q)) + " nonzeros needs " + std::to_string(B) +
+                            " co-resident blocks; this device holds " + std::to_string(h->long_capacity));
+        if (cur.nblocks + B > h->long_capacity) {
+            plan->rounds.push_back(cur);
+            cur = BinPlan::Round{(int)lw.size(), 0, 0, 0};
+        }
+        for (int p = 0; p < B; ++p) lw.push_back(LongWork{q, p, B, cur.ngroups});
+        cur.nblocks += B;
+        cur.ngroups += 1;
+        cur.pmax = std::max(cur.pmax, B);
+    }
+    if (cur.nblocks > 0) plan->rounds.push_back(cur);
+    for (const auto& r : plan->rounds) {
+        plan->max_groups = std::max(plan->max_groups, r.ngroups);
+        plan->max_pmax = std::max(plan->max_pmax, r.pmax);
+    }
+    if (!lw.empty()) {
+        HIP_TRY(h, dalloc(&plan->long_work, lw.size()));
+        HIP_TRY(h, hipMemcpy(plan->long_work, lw.data(), lw.size() * sizeof(LongWork), hipMemcpyHostToDevice));
+    }
     return NMFKL_OK;
 }
 
@@ -189,8 +275,10 @@ SweepArgs sweep_args(nmfkl_handle* h, bool fhalf) {
 // Model values at the nonzeros in CSC order from scratch (the objective's SDDMM pass).
 int refresh_model(nmfkl_handle* h) {
     const nmfkl_problem& pr = h->prob;
+    const int tm = timer_begin(h, NMFKL_T_MODEL);
     HIP_TRY(h, launch_model_objective(pr.csc_ptr, pr.csc_idx, pr.csc_val, pr.m, pr.W, pr.F, pr.r,
                                       h->Mcsc, h->obj_partials, h->obj_blocks, h->stream));
+    timer_end(h, tm);
     h->model = kModelCscFresh;
     return NMFKL_OK;
 }
@@ -200,7 +288,6 @@ int half_sweep(nmfkl_handle* h, int32_t t, bool fhalf) {
     if (t < 0) return fail(h, NMFKL_E_INVAL, "t must be >= 0");
     const nmfkl_problem& pr = h->prob;
     const BinPlan& plan = fhalf ? h->binF : h->binW;
-    if (plan.heavy) return fail(h, NMFKL_E_UNSUPPORTED, "segments longer than the fused launch supports");
     if (fhalf) {
         const bool fresh_needed = h->model == kModelNone || (h->prm.refresh_model && h->model != kModelCscFresh);
         if (fresh_needed) {
@@ -213,9 +300,11 @@ int half_sweep(nmfkl_handle* h, int32_t t, bool fhalf) {
     }
     const float* A = fhalf ? pr.W : pr.F;
     const int64_t P = fhalf ? pr.n : pr.m;
+    const int ts = timer_begin(h, fhalf ? NMFKL_T_SUMS_F : NMFKL_T_SUMS_W);
     HIP_TRY(h, launch_make_order(h->prm.seed, (uint64_t)t, 0, pr.r, h->ids, h->stream));
     HIP_TRY(h, launch_permute_colsum(A, P, pr.r, h->Sp, h->ids, h->Ap, h->partials, h->sum_blocks, h->stream));
     HIP_TRY(h, launch_finalize_sums(h->partials, h->sum_blocks, pr.r, h->sumA, h->stream));
+    timer_end(h, ts);
     SweepArgs a = sweep_args(h, fhalf);
     if (fhalf) {
         const bool from_csc = h->model == kModelCsc || h->model == kModelCscFresh;
@@ -229,8 +318,14 @@ int half_sweep(nmfkl_handle* h, int32_t t, bool fhalf) {
         a.Mmap = from_csr ? nullptr : h->csr2csc;
         a.Mout = h->Mcsr;
     }
-    HIP_TRY(h, launch_sweep_fused(a, plan.work + plan.nblocks[0], plan.segs, plan.nblocks[1], 1, h->stream));
-    HIP_TRY(h, launch_sweep_fused(a, plan.work, plan.segs, plan.nblocks[0], 0, h->stream));
+    const int tl = plan.rounds.empty() ? -1 : timer_begin(h, fhalf ? NMFKL_T_LONG_F : NMFKL_T_LONG_W);
+    for (const auto& rd : plan.rounds)
+        HIP_TRY(h, launch_sweep_long(a, plan.long_work + rd.first, rd.nblocks, h->coop_partials,
+                                     h->coop_counters, rd.ngroups, h->dev_err, rd.pmax, h->stream));
+    timer_end(h, tl);
+    const int tf = plan.nblocks ? timer_begin(h, fhalf ? NMFKL_T_FUSED_F : NMFKL_T_FUSED_W) : -1;
+    HIP_TRY(h, launch_sweep_fused(a, plan.work, plan.segs, plan.nblocks, h->stream));
+    timer_end(h, tf);
     h->model = fhalf ? kModelCsc : kModelCsr;
     return NMFKL_OK;
 }
@@ -254,6 +349,7 @@ int nmfkl_params_default(nmfkl_params* p) {
     p->foldin_tol = 1e-5;
     p->refresh_model = 1;
     p->collect_stats = 0;
+    p->collect_timings = 0;
     return NMFKL_OK;
 }
 
@@ -361,13 +457,41 @@ int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_str
     CREATE_HIP(hipMemsetAsync(h->stats, 0, 6 * sizeof(unsigned long long), h->stream));
     CREATE_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->host_scal), sizeof(double), hipHostMallocDefault));
     {
+        int ncu = 0;
+        CREATE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
+        h->long_capacity = long_kernel_blocks_per_cu() * ncu;
+        if (h->long_capacity <= 0) {
+            fail(h, NMFKL_E_DEVICE, "occupancy query of the long-segment kernel failed");
+            return bail(NMFKL_E_DEVICE);
+        }
         int rc = plan_bins(h, pr.csc_ptr, pr.m, &h->binF);
         if (rc) return bail(rc);
         rc = plan_bins(h, pr.csr_ptr, pr.n, &h->binW);
         if (rc) return bail(rc);
+        const int groups = std::max(h->binF.max_groups, h->binW.max_groups);
+        const int pmax = std::max(h->binF.max_pmax, h->binW.max_pmax);
+        CREATE_HIP(dalloc(&h->coop_partials, (size_t)std::max(groups, 1) * 4 * std::max(pmax, 1)));
+        CREATE_HIP(dalloc(&h->coop_counters, std::max(groups, 1)));
+        CREATE_HIP(dalloc(&h->dev_err, 1));
+        CREATE_HIP(hipMemsetAsync(h->dev_err, 0, sizeof(unsigned), h->stream));
     }
     CREATE_HIP(hipStreamSynchronize(h->stream));
 #undef CREATE_HIP
+    {
+        const double r = pr.r;
+        auto& k = h->timings.k;
+        k[NMFKL_T_FUSED_F].gather_bytes = h->binF.fused_bytes;
+        k[NMFKL_T_FUSED_F].updates = h->binF.fused_updates;
+        k[NMFKL_T_LONG_F].gather_bytes = h->binF.long_bytes;
+        k[NMFKL_T_LONG_F].updates = h->binF.long_updates;
+        k[NMFKL_T_FUSED_W].gather_bytes = h->binW.fused_bytes;
+        k[NMFKL_T_FUSED_W].updates = h->binW.fused_updates;
+        k[NMFKL_T_LONG_W].gather_bytes = h->binW.long_bytes;
+        k[NMFKL_T_LONG_W].updates = h->binW.long_updates;
+        k[NMFKL_T_SUMS_F].gather_bytes = (double)pr.n * r * 4.0 * 2.0;   // read W, write its copy
+        k[NMFKL_T_SUMS_W].gather_bytes = (double)pr.m * r * 4.0 * 2.0;
+        k[NMFKL_T_MODEL].gather_bytes = (double)nnz * (16.0 + 4.0 * r) + (double)pr.m * (8.0 + 4.0 * r);
+    }
     h->model = kModelNone;
     *out = h;
     return NMFKL_OK;
@@ -402,7 +526,10 @@ int nmfkl_objective(nmfkl_handle* h, double* D_out) {
     std::vector<double> sums(2 * (size_t)pr.r);
     HIP_TRY(h, hipMemcpyAsync(h->host_scal, h->dscal, sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipMemcpyAsync(sums.data(), h->sums2, sums.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    unsigned derr = 0;
+    HIP_TRY(h, hipMemcpyAsync(&derr, h->dev_err, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
+    if (derr) return fail(h, NMFKL_E_DEVICE, "a cross-block wait of a long segment timed out");
     part = *h->host_scal;
     double total = 0.0;
     for (int k = 0; k < pr.r; ++k) {
@@ -428,6 +555,24 @@ int nmfkl_get_stats(nmfkl_handle* h, nmfkl_stats* out) {
     out->halvings = (int64_t)c[3];
     out->rejects = (int64_t)c[4];
     out->tmax_hits = (int64_t)c[5];
+    return NMFKL_OK;
+}
+
+int nmfkl_get_timings(nmfkl_handle* h, nmfkl_timings* out) {
+    if (!h) return fail(nullptr, NMFKL_E_INVAL, "null handle");
+    if (!out) return fail(h, NMFKL_E_INVAL, "out is null");
+    HIP_TRY(h, resolve_timings(h));
+    *out = h->timings;
+    return NMFKL_OK;
+}
+
+int nmfkl_reset_timings(nmfkl_handle* h) {
+    if (!h) return fail(nullptr, NMFKL_E_INVAL, "null handle");
+    HIP_TRY(h, resolve_timings(h));
+    for (auto& k : h->timings.k) {
+        k.ms_total = 0.0;
+        k.launches = 0;
+    }
     return NMFKL_OK;
 }
 

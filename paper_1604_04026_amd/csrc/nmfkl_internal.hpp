@@ -93,10 +93,24 @@ struct BlockWork {
 
 // The (G lanes per segment, E elements per lane) variants of the fused launch.
 struct Variant { int G, E; };
-constexpr int kNumVariants = 6;
-constexpr Variant kVariants[kNumVariants] = {{8, 4}, {16, 4}, {32, 4}, {64, 4}, {256, 4}, {256, 8}};
+constexpr int kNumVariants = 5;
+constexpr Variant kVariants[kNumVariants] = {{8, 4}, {16, 4}, {32, 4}, {64, 4}, {256, 4}};
 constexpr int kFusedThreads = 256;
-constexpr int kMaxFusedLength = 2048;   // 256 * 8
+constexpr int kMaxFusedLength = 1024;   // 256 * 4
+
+// Longer segments: blocks of kLongThreads threads, kLongE nonzeros per thread; a segment
+// spans B = ceil(L / kLongCapacity) cooperating blocks.
+constexpr int kLongThreads = 1024;
+constexpr int kLongE = 4;
+constexpr int kLongCapacity = kLongThreads * kLongE;
+
+// A block of a long-segment launch.
+struct LongWork {
+    int32_t seg;    // segment id
+    int32_t part;   // this block's part, 0 <= part < B
+    int32_t B;      // blocks cooperating on the segment
+    int32_t group;  // index of the segment's reduction slot in this launch
+};
 
 // Launch wrappers (defined with the kernels).  All enqueue on `stream`.
 hipError_t launch_make_order(uint64_t seed, uint64_t t, uint64_t stream_id, int r, int32_t* ids,
@@ -106,9 +120,14 @@ hipError_t launch_permute_colsum(const float* A, int64_t P, int r, int Sp, const
 hipError_t launch_finalize_sums(const double* partials, int nblocks, int r, double* out,
                                 hipStream_t stream);
 hipError_t launch_sweep_fused(const SweepArgs& a, const BlockWork* work, const int32_t* segs,
-                              int nblocks, int family, hipStream_t stream);
-// Kernel family of a variant (0: the E = 4 variants, 1: the 256 x 8 variant).
-constexpr int family_of(int variant) { return variant == kNumVariants - 1 ? 1 : 0; }
+                              int nblocks, hipStream_t stream);
+// Cooperative launch over long segments; zeroes the group counters first.  partials holds
+// 4 * pmax doubles per group (pmax = largest B in the launch).
+hipError_t launch_sweep_long(const SweepArgs& a, const LongWork* work, int nblocks, double* partials,
+                             unsigned* counters, int ngroups, unsigned* err, int pmax,
+                             hipStream_t stream);
+// Co-resident blocks of the long-segment kernel per compute unit (0 on failure).
+int long_kernel_blocks_per_cu();
 hipError_t launch_model_objective(const int64_t* csc_ptr, const int32_t* csc_idx,
                                   const float* csc_val, int m, const float* W, const float* F, int r,
                                   double* Mcsc, double* partials, int nblocks, hipStream_t stream);

@@ -140,18 +140,30 @@ struct Elems {
     float v[E], w[E], u[E];
 };
 
-// Segment-wide all-reduce of (S1, S2).  Segments of up to 64 lanes stay inside one wave;
-// a 256-lane segment (the whole block) adds the four wave sums through LDS in wave order.
+// ---- segment-wide all-reduce of (S1, S2): three reducers with one interface -----------
+// Every lane of a segment receives bit-identical sums, so every lane takes the same Newton
+// decisions.
+
+// Segments of G <= 64 lanes inside one wave: DPP / lane shuffles only.
 template <int G>
-__device__ __forceinline__ float2 seg_sum(float2 s, float2* red, int& parity) {
-    if constexpr (G <= 64) {
+struct WaveReducer {
+    __device__ __forceinline__ float2 sum(float2 s) {
         s.x = group_sum<G>(s.x);
         s.y = group_sum<G>(s.y);
         return s;
-    } else {
+    }
+};
+
+// One segment per block of NT threads: wave sums, then the NT/64 wave sums through LDS in
+// wave order (double-buffered by parity, one barrier per reduction).
+template <int NT>
+struct BlockReducer {
+    float2* red;  // LDS, 2 * NT/64 entries
+    int parity;
+    __device__ __forceinline__ float2 sum(float2 s) {
         s.x = group_sum<64>(s.x);
         s.y = group_sum<64>(s.y);
-        constexpr int W = G / 64;
+        constexpr int W = NT / 64;
         const int wv = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) red[parity * W + wv] = s;
         __syncthreads();
@@ -164,13 +176,83 @@ __device__ __forceinline__ float2 seg_sum(float2 s, float2* red, int& parity) {
         parity ^= 1;
         return t;
     }
+};
+
+// A long segment split over B co-resident blocks (cooperative launch).  Each reduction:
+// block sum; thread 0 publishes it (float64) in slot parity of the group's partials and
+// arrives on the group's counter with release semantics, then waits (acquire) until all B
+// blocks arrived; wave 0 reads the B partials, lane b holding partials b, b+64, ..., and
+// all-reduces them with a fixed butterfly, so every block obtains the same total.  The wait
+// is bounded: after kSpinLimit polls, or as soon as any block has recorded an error, the
+// block records an error and continues (the host reports it at the next synchronising call).
+constexpr unsigned kSpinLimit = 1u << 20;
+
+__device__ __forceinline__ double shfl_xor_f64(double v, int m) {
+    int2 p = *reinterpret_cast<int2*>(&v);
+    p.x = __shfl_xor(p.x, m);
+    p.y = __shfl_xor(p.y, m);
+    return *reinterpret_cast<double*>(&p);
 }
 
+template <int NT>
+struct CoopReducer {
+    BlockReducer<NT> blk;
+    double* bcast;      // LDS, 2 doubles
+    double* partials;   // global: [2][B][2] for this group
+    unsigned* counter;  // global: arrivals of this group
+    unsigned* err;      // global error flags
+    int B, part;
+    unsigned round;
+    __device__ __forceinline__ float2 sum(float2 s) {
+        const float2 b = blk.sum(s);
+        if (B == 1) return b;
+        const unsigned slot = round & 1u;
+        if (threadIdx.x == 0) {
+            double* p = partials + ((size_t)slot * B + part) * 2;
+            __hip_atomic_store(p, (double)b.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(p + 1, (double)b.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned target = (round + 1u) * (unsigned)B;
+            unsigned spins = 0;
+            while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                __builtin_amdgcn_s_sleep(1);
+                // give up on a timeout, or at once once any block has given up
+                if (++spins > kSpinLimit ||
+                    __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                    atomicOr(err, 1u);
+                    break;
+                }
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            double sx = 0.0, sy = 0.0;
+            for (int q = threadIdx.x; q < B; q += 64) {
+                const double* p = partials + ((size_t)slot * B + q) * 2;
+                sx += __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                sy += __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+#pragma unroll
+            for (int m = 1; m < 64; m <<= 1) {
+                sx += shfl_xor_f64(sx, m);
+                sy += shfl_xor_f64(sy, m);
+            }
+            if (threadIdx.x == 0) {
+                bcast[0] = sx;
+                bcast[1] = sy;
+            }
+        }
+        __syncthreads();
+        ++round;
+        return make_float2((float)bcast[0], (float)bcast[1]);
+    }
+};
+
 // Alg. 2's inner loop for one coordinate s of one segment.  tk[e] holds A[i_l][s] for the
-// lane's nonzeros.  xs points at the segment's x in LDS (permuted order).  Returns counters.
-template <int G, int E>
+// lane's nonzeros.  xs points at the segment's x in LDS (permuted order).
+template <int E, class Red>
 __device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s, const float (&tk)[E],
-                                                Elems<E>& st, float* xs, float2* red, int& parity,
+                                                Elems<E>& st, float* xs, Red& red,
                                                 unsigned (&cnt)[6]) {
     float xk = xs[s];
     const double sA = a.sumA[s];
@@ -180,7 +262,7 @@ __device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s, const
         acc.x = fmaf(tk[e], st.w[e], acc.x);
         acc.y = fmaf(tk[e] * tk[e], st.u[e], acc.y);
     }
-    acc = seg_sum<G>(acc, red, parity);
+    acc = red.sum(acc);
     double P = sA + (double)a.alpha * xk + (double)a.beta;
     double g = P - (double)acc.x;
     float h = acc.y + a.alpha;
@@ -217,7 +299,7 @@ __device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s, const
                 t2.x = fmaf(tk[e], ww, t2.x);
                 t2.y = fmaf(tk[e] * tk[e], un[e], t2.y);
             }
-            t2 = seg_sum<G>(t2, red, parity);
+            t2 = red.sum(t2);
             cnt[1] += 1;
             const float xt = xk + d;
             Pn = sA + (double)a.alpha * xt + (double)a.beta;
@@ -250,12 +332,13 @@ __device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s, const
     xs[s] = xk;
 }
 
-template <int E>
-__device__ __forceinline__ void load_chunk(const SweepArgs& a, const Elems<E>& st, int L, int lane,
-                                           int G, int c, float4 (&t)[E][2]) {
+// Elements handled by this lane: l = lo + lane + STRIDE * e, e < E, restricted to l < L.
+template <int E, int STRIDE>
+__device__ __forceinline__ void load_chunk(const SweepArgs& a, const Elems<E>& st, int L, int lo,
+                                           int lane, int c, float4 (&t)[E][2]) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        if (lane + G * e < L) {
+        if (lo + lane + STRIDE * e < L) {
             const float4* p = reinterpret_cast<const float4*>(a.Ap + (int64_t)st.id[e] * a.Sp + c * kChunk);
             t[e][0] = p[0];
             t[e][1] = p[1];
@@ -277,10 +360,11 @@ __device__ __forceinline__ float comp(const float4 (&t)[E][2], int e, int cc) {
     }
 }
 
-// One segment per group of G lanes.  `slot` is the segment's position within the block.
-template <int G, int E>
-__device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool active, int lane, float* xs,
-                              float2* red) {
+// Alg. 2 on one segment (or on this block's part [lo, lo + STRIDE*E) of a long segment).
+// PREFETCH: keep the next tile chunk in flight while the current one is processed.
+template <int STRIDE, int E, bool PREFETCH, class Red>
+__device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool active, int lane,
+                                              int lo, bool count_stats, float* xs, Red& red) {
     int64_t base = 0;
     int L = 0;
     if (active) {
@@ -290,7 +374,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool 
     Elems<E> st;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const int l = lane + G * e;
+        const int l = lo + lane + STRIDE * e;
         if (l < L) {
             const int64_t q = base + l;
             st.id[e] = a.idx[q];
@@ -307,12 +391,12 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool 
     }
     if (!active) return;
     unsigned cnt[6] = {0, 0, 0, 0, 0, 0};
-    int parity = 0;
     const int nchunks = (a.r + kChunk - 1) / kChunk;
-    float4 cur[E][2], nxt[E][2];
-    load_chunk<E>(a, st, L, lane, G, 0, cur);
+    float4 cur[E][2];
+    load_chunk<E, STRIDE>(a, st, L, lo, lane, 0, cur);
     for (int c = 0; c < nchunks; ++c) {
-        if (c + 1 < nchunks) load_chunk<E>(a, st, L, lane, G, c + 1, nxt);
+        float4 nxt[E][2];
+        if (PREFETCH && c + 1 < nchunks) load_chunk<E, STRIDE>(a, st, L, lo, lane, c + 1, nxt);
 #pragma unroll
         for (int cc = 0; cc < kChunk; ++cc) {
             const int s = c * kChunk + cc;
@@ -320,22 +404,26 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool 
                 float tk[E];
 #pragma unroll
                 for (int e = 0; e < E; ++e) tk[e] = comp<E>(cur, e, cc);
-                coordinate_step<G, E>(a, s, tk, st, xs, red, parity, cnt);
+                coordinate_step<E>(a, s, tk, st, xs, red, cnt);
             }
         }
+        if (PREFETCH) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            cur[e][0] = nxt[e][0];
-            cur[e][1] = nxt[e][1];
+            for (int e = 0; e < E; ++e) {
+                cur[e][0] = nxt[e][0];
+                cur[e][1] = nxt[e][1];
+            }
+        } else if (c + 1 < nchunks) {
+            load_chunk<E, STRIDE>(a, st, L, lo, lane, c + 1, cur);
         }
     }
     // write back the model at the nonzeros (this segment order)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const int l = lane + G * e;
+        const int l = lo + lane + STRIDE * e;
         if (l < L) a.Mout[base + l] = st.ax[e];
     }
-    if (a.stats && lane == 0) {
+    if (a.stats && count_stats && lane == 0) {
 #pragma unroll
         for (int q = 0; q < 6; ++q) atomicAdd(&a.stats[q], (unsigned long long)cnt[q]);
     }
@@ -343,8 +431,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool 
 
 template <int G, int E>
 __device__ __forceinline__ void sweep_block(const SweepArgs& a, const BlockWork& wk, const int32_t* segs,
-                            float* xs_all, float2* red) {
-    constexpr int SPB = kFusedThreads / G;  // segments per block
+                                            float* xs_all, float2* red_lds) {
     const int slot = threadIdx.x / G;
     const int lane = threadIdx.x % G;
     const bool active = slot < wk.count;
@@ -354,44 +441,94 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const BlockWork&
     if (active)
         for (int s = lane; s < a.r; s += G) xs[s] = a.X[(int64_t)seg * a.r + a.ids[s]];
     __syncthreads();
-    sweep_segment<G, E>(a, seg, active, lane, xs, red);
-    if constexpr (G > 64) __syncthreads();
+    if constexpr (G <= 64) {
+        WaveReducer<G> red;
+        sweep_segment<G, E, true>(a, seg, active, lane, 0, true, xs, red);
+    } else {
+        BlockReducer<G> red{red_lds, 0};
+        sweep_segment<G, E, true>(a, seg, active, lane, 0, true, xs, red);
+        __syncthreads();
+    }
     if (active)
         for (int s = lane; s < a.r; s += G) a.X[(int64_t)seg * a.r + a.ids[s]] = xs[s];
-    (void)SPB;
 }
 
-// Family 0: the E = 4 variants (segments up to 1024 nonzeros) in one launch, each block
-// picking its variant from the work table.  Family 1: 256 lanes x 8 elements (up to 2048),
-// compiled as its own kernel so that its larger register footprint does not lower the
-// occupancy of family 0.
-template <int FAMILY>
+// The fused binned launch: each block picks its (G, E) variant from the work table.
 __global__ void __launch_bounds__(kFusedThreads, 2)
 k_sweep_fused(SweepArgs a, const BlockWork* __restrict__ work, const int32_t* __restrict__ segs) {
     __shared__ float xs_all[(kFusedThreads / 8) * NMFKL_R_MAX];
     __shared__ float2 red[2 * (kFusedThreads / 64)];
     const BlockWork wk = work[blockIdx.x];
-    if constexpr (FAMILY == 0) {
-        switch (wk.variant) {
-            case 0: sweep_block<8, 4>(a, wk, segs, xs_all, red); break;
-            case 1: sweep_block<16, 4>(a, wk, segs, xs_all, red); break;
-            case 2: sweep_block<32, 4>(a, wk, segs, xs_all, red); break;
-            case 3: sweep_block<64, 4>(a, wk, segs, xs_all, red); break;
-            default: sweep_block<256, 4>(a, wk, segs, xs_all, red); break;
-        }
-    } else {
-        sweep_block<256, 8>(a, wk, segs, xs_all, red);
+    switch (wk.variant) {
+        case 0: sweep_block<8, 4>(a, wk, segs, xs_all, red); break;
+        case 1: sweep_block<16, 4>(a, wk, segs, xs_all, red); break;
+        case 2: sweep_block<32, 4>(a, wk, segs, xs_all, red); break;
+        case 3: sweep_block<64, 4>(a, wk, segs, xs_all, red); break;
+        default: sweep_block<256, 4>(a, wk, segs, xs_all, red); break;
     }
 }
 
 hipError_t launch_sweep_fused(const SweepArgs& a, const BlockWork* work, const int32_t* segs,
-                              int nblocks, int family, hipStream_t stream) {
+                              int nblocks, hipStream_t stream) {
     if (nblocks <= 0) return hipSuccess;
-    if (family == 0)
-        hipLaunchKernelGGL(k_sweep_fused<0>, dim3(nblocks), dim3(kFusedThreads), 0, stream, a, work, segs);
-    else
-        hipLaunchKernelGGL(k_sweep_fused<1>, dim3(nblocks), dim3(kFusedThreads), 0, stream, a, work, segs);
+    hipLaunchKernelGGL(k_sweep_fused, dim3(nblocks), dim3(kFusedThreads), 0, stream, a, work, segs);
     return hipGetLastError();
+}
+
+// Long segments: kLongThreads threads x kLongE elements per block; a segment of L nonzeros
+// takes B = ceil(L / (kLongThreads*kLongE)) blocks that cooperate through CoopReducer.  All
+// blocks of one launch are co-resident (cooperative launch), so every wait ends.
+__global__ void __launch_bounds__(kLongThreads)
+k_sweep_long(SweepArgs a, const LongWork* __restrict__ work, double* __restrict__ partials,
+             unsigned* __restrict__ counters, unsigned* __restrict__ err, int pmax) {
+    __shared__ float xs[NMFKL_R_MAX];
+    __shared__ float2 red_lds[2 * (kLongThreads / 64)];
+    __shared__ double bcast[2];
+    const LongWork wk = work[blockIdx.x];
+    const int lane = threadIdx.x;
+    for (int s = lane; s < a.r; s += kLongThreads) xs[s] = a.X[(int64_t)wk.seg * a.r + a.ids[s]];
+    __syncthreads();
+    CoopReducer<kLongThreads> red;
+    red.blk.red = red_lds;
+    red.blk.parity = 0;
+    red.bcast = bcast;
+    red.partials = partials + (size_t)wk.group * 2 * 2 * pmax;
+    red.counter = counters + wk.group;
+    red.err = err;
+    red.B = wk.B;
+    red.part = wk.part;
+    red.round = 0;
+    sweep_segment<kLongThreads, kLongE, false>(a, wk.seg, true, lane, wk.part * kLongThreads * kLongE,
+                                               wk.part == 0, xs, red);
+    __syncthreads();
+    if (wk.part == 0)
+        for (int s = lane; s < a.r; s += kLongThreads) a.X[(int64_t)wk.seg * a.r + a.ids[s]] = xs[s];
+}
+
+__global__ void k_zero_u32(unsigned* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_sweep_long(const SweepArgs& a, const LongWork* work, int nblocks, double* partials,
+                             unsigned* counters, int ngroups, unsigned* err, int pmax,
+                             hipStream_t stream) {
+    if (nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u32, dim3((ngroups + 255) / 256), dim3(256), 0, stream, counters, ngroups);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    SweepArgs aa = a;
+    void* args[] = {&aa, &work, &partials, &counters, &err, &pmax};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_sweep_long), dim3(nblocks),
+                                      dim3(kLongThreads), args, 0, stream);
+}
+
+int long_kernel_blocks_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_sweep_long),
+                                                     kLongThreads, 0) != hipSuccess)
+        return 0;
+    return nb;
 }
 
 // ------------------------------------------------- model at the nonzeros + objective

@@ -193,3 +193,81 @@ def test_stats_counters():
     P.nmfkl_destroy(h)
     assert st["coords"] == (prob.m + prob.n) * prob.r
     assert st["evals"] >= st["coords"] and st["steps"] > 0
+
+
+def long_corpus(seed=0):
+    """Rows up to ~20k nonzeros: single-block (1025..4096) and multi-block long segments."""
+    n, m, r = 2000, 20000, 12
+    ptr, idx, val = workloads.corpus(n, m, 80.0, 1.0, 2000, 1.1, 0.6, seed=seed, tag=8)
+    return workloads._problem(n, m, r, ptr, idx, val, seed, 8, {"name": f"corpus {n}x{m} r={r}"})
+
+
+def test_long_segments_step_and_trajectory():
+    prob = long_corpus()
+    R = np.diff(prob.csr_ptr)
+    assert R.max() > 4 * 4096 and ((R > 1024) & (R <= 4096)).any()
+    t = 1
+    ids = oracle.permutation(0, t, 0, prob.r)
+    Wo, _, _ = oracle.sweep_W(prob, prob.F0.astype(np.float64), prob.W0.astype(np.float64), ids)
+    Wg = gpu_half(prob, prob.W0, prob.F0, t, "W")
+    rows_long = R > 1024
+    e_all, e_long = relf(Wg, Wo), relf(Wg[rows_long], Wo[rows_long])
+    print(f"long W-half: rel {e_all:.2e}, long rows rel {e_long:.2e}, flips {flips(Wg, Wo)}")
+    assert e_all <= 1e-4 and e_long <= 1e-4
+    sweeps = 5
+    dev = P.upload(prob, "cuda")
+    h = P.nmfkl_create(dev)
+    Dg = []
+    for t in range(sweeps):
+        P.nmfkl_sweep_F(h, t)
+        P.nmfkl_sweep_W(h, t)
+        Dg.append(P.nmfkl_objective(h))
+    Wg, Fg = dev.W.cpu().numpy(), dev.F.cpu().numpy()
+    P.nmfkl_destroy(h)
+    Wo, Fo, Do = oracle.run(prob, sweeps)
+    relD = np.abs(np.array(Dg) - Do) / Do
+    print(f"long trajectory: D rel {np.array2string(relD, precision=1)}; W {relf(Wg, Wo):.2e} F {relf(Fg, Fo):.2e}")
+    assert np.all(relD <= 1e-5) and relf(Wg, Wo) <= 1e-4 and relf(Fg, Fo) <= 1e-4
+
+
+@pytest.fixture(scope="module")
+def corpus_full():
+    return workloads.config(1, seed=0)
+
+
+def test_sampled_parity_full_size_corpus(corpus_full):
+    """The 50,000 x 100,000, r = 50 corpus in the launch configuration the benchmark times:
+    one F-half and one W-half on the GPU from (W0, F0); the oracle recomputes sampled
+    columns and rows one by one (the 20 heaviest rows included) from the same state."""
+    prob = corpus_full
+    t = 0
+    ids = oracle.permutation(0, t, 0, prob.r)
+    dev = P.upload(prob, "cuda")
+    h = P.nmfkl_create(dev)
+    P.nmfkl_sweep_F(h, t)
+    Fg = dev.F.cpu().numpy()
+    P.nmfkl_sweep_W(h, t)
+    Wg = dev.W.cpu().numpy()
+    P.nmfkl_destroy(h)
+    W0, F0 = prob.W0.astype(np.float64), prob.F0.astype(np.float64)
+    rng = np.random.default_rng(11)
+    sumW = oracle.factor_sums(W0)
+    cols = rng.choice(prob.m, 3000, replace=False)
+    Fo = np.array([oracle.alg2(prob.csc_idx[prob.csc_ptr[j]:prob.csc_ptr[j + 1]],
+                               prob.csc_val[prob.csc_ptr[j]:prob.csc_ptr[j + 1]], W0, sumW, F0[j], ids)[0]
+                   for j in cols])
+    eF = relf(Fg[cols], Fo)
+    # W-half rows from the GPU's F (the state the GPU W-half started from)
+    F1 = Fg.astype(np.float64)
+    sumF = oracle.factor_sums(F1)
+    R = np.diff(prob.csr_ptr)
+    heavy = np.sort(np.argsort(R)[-20:])
+    rows = np.unique(np.concatenate([heavy, rng.choice(prob.n, 1000, replace=False)]))
+    Wo = np.array([oracle.alg2(prob.csr_idx[prob.csr_ptr[i]:prob.csr_ptr[i + 1]],
+                               prob.csr_val[prob.csr_ptr[i]:prob.csr_ptr[i + 1]], F1, sumF, W0[i], ids)[0]
+                   for i in rows])
+    eW = relf(Wg[rows], Wo)
+    eH = relf(Wg[heavy], Wo[np.isin(rows, heavy)])
+    print(f"full corpus sampled: F rel {eF:.2e} (3000 cols), W rel {eW:.2e} ({rows.size} rows), "
+          f"20 heaviest rows rel {eH:.2e}; flips F {flips(Fg[cols], Fo)} W {flips(Wg[rows], Wo)}")
+    assert eF <= 1e-4 and eW <= 1e-4 and eH <= 1e-4
