@@ -65,11 +65,16 @@ typedef struct nmfkl_params {
     uint64_t seed;   /* Philox key of the coordinate orders (0) */
     int32_t foldin_max_passes; /* fold-in: passes at most (200) */
     double foldin_tol;         /* fold-in: stop when the KL decrease <= tol * KL (1e-5) */
-    int32_t refresh_model;     /* 1: recompute the model at the nonzeros from W and F at the start of
-                                  every nmfkl_sweep_F unless nmfkl_objective just did (default);
-                                  0: carry it from the previous half (identical in exact arithmetic) */
+    int32_t refresh_model;     /* 0 (default): the model values at the nonzeros (float64) are carried
+                                  from one half-sweep to the next and recomputed only for the first
+                                  half-sweep or after nmfkl_invalidate_model; 1: recomputed from W and
+                                  F at the start of every nmfkl_sweep_F (unless nmfkl_objective just
+                                  did).  Identical in exact arithmetic; the carried values differ from
+                                  fresh products only by the float32 rounding of factor updates */
     int32_t collect_stats;     /* 1: count derivative evaluations / steps / guard events (slower) */
     int32_t collect_timings;   /* 1: bracket every launch group with HIP events (nmfkl_get_timings) */
+    int32_t tuning;            /* implementation choices that do not change results; bit 0: batched
+                                  (lookahead) derivative sums also for segments of 257..1024 nonzeros */
 } nmfkl_params;
 
 typedef struct nmfkl_problem {
@@ -154,6 +159,13 @@ int nmfkl_sweep_W(nmfkl_handle* h, int32_t t);
  * v log(v/M) - v with M = W_i . F_j, plus sum(W^T F) = sumW . sumF.  Synchronises.
  * +inf if some nonzero has M = 0; NMFKL_E_NONFINITE if a factor holds NaN/Inf. */
 int nmfkl_objective(nmfkl_handle* h, double* D_out);
+
+/* eq. 1 for the current W, F using the model values the handle carries between halves
+ * (no pass over the factors): sum over the nonzeros of v log(v/M) - v, plus sumW . sumF.
+ * Differs from nmfkl_objective by the float32 rounding of factor updates accumulated in the
+ * carried values (about 1e-7 relative after tens of sweeps).  Synchronises.  Falls back to
+ * nmfkl_objective when no model is carried yet. */
+int nmfkl_objective_carried(nmfkl_handle* h, double* D_out);
 
 /* Tell the handle that the caller changed W or F outside the library: the model values
  * the handle carries between halves are recomputed before the next half-sweep. */

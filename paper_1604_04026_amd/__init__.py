@@ -28,7 +28,7 @@ R_MAX = 128
 
 EXPORTED_SYMBOLS = [
     "nmfkl_params_default", "nmfkl_permutation", "nmfkl_create", "nmfkl_sweep_F", "nmfkl_sweep_W",
-    "nmfkl_objective", "nmfkl_invalidate_model", "nmfkl_get_stats", "nmfkl_get_timings",
+    "nmfkl_objective", "nmfkl_objective_carried", "nmfkl_invalidate_model", "nmfkl_get_stats", "nmfkl_get_timings",
     "nmfkl_reset_timings", "nmfkl_destroy", "nmfkl_last_error",
 ]
 
@@ -50,7 +50,7 @@ class NmfklParams(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("foldin_max_passes", ctypes.c_int32), ("foldin_tol", ctypes.c_double),
         ("refresh_model", ctypes.c_int32), ("collect_stats", ctypes.c_int32),
-        ("collect_timings", ctypes.c_int32),
+        ("collect_timings", ctypes.c_int32), ("tuning", ctypes.c_int32),
     ]
 
 
@@ -110,6 +110,7 @@ def load(path: str | None = None):
     lib.nmfkl_sweep_F.argtypes = [vp, i32]
     lib.nmfkl_sweep_W.argtypes = [vp, i32]
     lib.nmfkl_objective.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    lib.nmfkl_objective_carried.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     lib.nmfkl_invalidate_model.argtypes = [vp]
     lib.nmfkl_get_stats.argtypes = [vp, ctypes.POINTER(NmfklStats)]
     lib.nmfkl_get_timings.argtypes = [vp, ctypes.POINTER(NmfklTimings)]
@@ -237,6 +238,12 @@ def nmfkl_sweep_W(h: Handle, t: int):
 def nmfkl_objective(h: Handle) -> float:
     d = ctypes.c_double()
     _check(load().nmfkl_objective(h._ptr, ctypes.byref(d)), h._ptr)
+    return d.value
+
+
+def nmfkl_objective_carried(h: Handle) -> float:
+    d = ctypes.c_double()
+    _check(load().nmfkl_objective_carried(h._ptr, ctypes.byref(d)), h._ptr)
     return d.value
 
 

@@ -23,8 +23,11 @@ struct BinPlan {
     BlockWork* work = nullptr;  // device: blocks of the fused launch
     int32_t* segs = nullptr;    // device
     int nblocks = 0;
-    // long segments: cooperative launches ("rounds"), each within the co-residency capacity
-    LongWork* long_work = nullptr;  // device, all rounds concatenated
+    // long segments: those fitting one block in an ordinary launch (single_blocks entries at
+    // the start of long_work), the others in cooperative launches ("rounds"), each within
+    // the co-residency capacity
+    LongWork* long_work = nullptr;  // device: single-block entries, then all rounds
+    int single_blocks = 0;
     struct Round { int first, nblocks, ngroups, pmax; };
     std::vector<Round> rounds;
     int max_groups = 0, max_pmax = 0;
@@ -57,7 +60,7 @@ struct nmfkl_handle {
     double* host_scal = nullptr;  // pinned host scalar
     unsigned long long* stats = nullptr;
     double* coop_partials = nullptr;   // cross-block partial sums of long segments
-    unsigned* coop_counters = nullptr; // their arrival counters
+    unsigned* coop_counters = nullptr; // their arrival flags (one line per block)
     unsigned* dev_err = nullptr;       // device-side error flags (bounded waits)
     int long_capacity = 0;             // co-resident long-segment blocks
     BinPlan binF, binW;
@@ -204,9 +207,13 @@ int plan_bins(nmfkl_handle* h, const int64_t* dptr, int64_t Q, BinPlan* plan) {
 
     std::stable_sort(longs.begin(), longs.end(), [&](int32_t a, int32_t b) { return len(a) > len(b); });
     std::vector<LongWork> lw;
-    BinPlan::Round cur{0, 0, 0, 0};
+    for (int32_t q : longs)
+        if (len(q) <= kLongCapacity) lw.push_back(LongWork{q, 0, 1, 0});
+    plan->single_blocks = (int)lw.size();
+    BinPlan::Round cur{(int)lw.size(), 0, 0, 0};
     for (int32_t q : longs) {
         const int B = (int)((len(q) + kLongCapacity - 1) / kLongCapacity);
+        if (B == 1) continue;
         if (B > h->long_capacity)
             return fail(h, NMFKL_E_UNSUPPORTED,
                         "a segment of " + std::to_string(len(q)) + " nonzeros needs " + std::to_string(B) +
@@ -301,8 +308,9 @@ int half_sweep(nmfkl_handle* h, int32_t t, bool fhalf) {
     const float* A = fhalf ? pr.W : pr.F;
     const int64_t P = fhalf ? pr.n : pr.m;
     const int ts = timer_begin(h, fhalf ? NMFKL_T_SUMS_F : NMFKL_T_SUMS_W);
-    HIP_TRY(h, launch_make_order(h->prm.seed, (uint64_t)t, 0, pr.r, h->ids, h->stream));
-    HIP_TRY(h, launch_permute_colsum(A, P, pr.r, h->Sp, h->ids, h->Ap, h->partials, h->sum_blocks, h->stream));
+    OrderArg order{};
+    coordinate_order(h->prm.seed, (uint64_t)t, 0, pr.r, order.ids);
+    HIP_TRY(h, launch_permute_colsum(A, P, pr.r, h->Sp, order, h->ids, h->Ap, h->partials, h->sum_blocks, h->stream));
     HIP_TRY(h, launch_finalize_sums(h->partials, h->sum_blocks, pr.r, h->sumA, h->stream));
     timer_end(h, ts);
     SweepArgs a = sweep_args(h, fhalf);
@@ -318,13 +326,15 @@ int half_sweep(nmfkl_handle* h, int32_t t, bool fhalf) {
         a.Mmap = from_csr ? nullptr : h->csr2csc;
         a.Mout = h->Mcsr;
     }
-    const int tl = plan.rounds.empty() ? -1 : timer_begin(h, fhalf ? NMFKL_T_LONG_F : NMFKL_T_LONG_W);
+    const bool any_long = plan.single_blocks > 0 || !plan.rounds.empty();
+    const int tl = any_long ? timer_begin(h, fhalf ? NMFKL_T_LONG_F : NMFKL_T_LONG_W) : -1;
+    HIP_TRY(h, launch_sweep_long_single(a, plan.long_work, plan.single_blocks, h->stream));
     for (const auto& rd : plan.rounds)
         HIP_TRY(h, launch_sweep_long(a, plan.long_work + rd.first, rd.nblocks, h->coop_partials,
                                      h->coop_counters, rd.ngroups, h->dev_err, rd.pmax, h->stream));
     timer_end(h, tl);
     const int tf = plan.nblocks ? timer_begin(h, fhalf ? NMFKL_T_FUSED_F : NMFKL_T_FUSED_W) : -1;
-    HIP_TRY(h, launch_sweep_fused(a, plan.work, plan.segs, plan.nblocks, h->stream));
+    HIP_TRY(h, launch_sweep_fused(a, plan.work, plan.segs, plan.nblocks, (h->prm.tuning & 1) != 0, h->stream));
     timer_end(h, tf);
     h->model = fhalf ? kModelCsc : kModelCsr;
     return NMFKL_OK;
@@ -347,9 +357,10 @@ int nmfkl_params_default(nmfkl_params* p) {
     p->seed = 0;
     p->foldin_max_passes = 200;
     p->foldin_tol = 1e-5;
-    p->refresh_model = 1;
+    p->refresh_model = 0;
     p->collect_stats = 0;
     p->collect_timings = 0;
+    p->tuning = 0;
     return NMFKL_OK;
 }
 
@@ -470,8 +481,10 @@ int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_str
         if (rc) return bail(rc);
         const int groups = std::max(h->binF.max_groups, h->binW.max_groups);
         const int pmax = std::max(h->binF.max_pmax, h->binW.max_pmax);
-        CREATE_HIP(dalloc(&h->coop_partials, (size_t)std::max(groups, 1) * 4 * std::max(pmax, 1)));
-        CREATE_HIP(dalloc(&h->coop_counters, std::max(groups, 1)));
+        // k_sweep_long<true> addresses partials + group * (2 * pmax * kCoopValues) + ...
+        CREATE_HIP(dalloc(&h->coop_partials, (size_t)std::max(groups, 1) * 2 * std::max(pmax, 1) * kCoopValues));
+        // ... and flags + group * (pmax * kFlagStride) + part * kFlagStride
+        CREATE_HIP(dalloc(&h->coop_counters, (size_t)std::max(groups, 1) * std::max(pmax, 1) * kFlagStride));
         CREATE_HIP(dalloc(&h->dev_err, 1));
         CREATE_HIP(hipMemsetAsync(h->dev_err, 0, sizeof(unsigned), h->stream));
     }
@@ -507,17 +520,34 @@ int nmfkl_invalidate_model(nmfkl_handle* h) {
     return NMFKL_OK;
 }
 
-int nmfkl_objective(nmfkl_handle* h, double* D_out) {
+namespace {
+int objective_impl(nmfkl_handle* h, double* D_out, bool carried);
+}
+
+int nmfkl_objective(nmfkl_handle* h, double* D_out) { return objective_impl(h, D_out, false); }
+
+int nmfkl_objective_carried(nmfkl_handle* h, double* D_out) { return objective_impl(h, D_out, true); }
+
+namespace {
+int objective_impl(nmfkl_handle* h, double* D_out, bool carried) {
     if (!h) return fail(nullptr, NMFKL_E_INVAL, "null handle");
     if (!D_out) return fail(h, NMFKL_E_INVAL, "D_out is null");
     const nmfkl_problem& pr = h->prob;
     unsigned* flags = nullptr;
     // natural-order float64 column sums of W and F: sum over all cells of W^T F = sumW . sumF
-    HIP_TRY(h, launch_permute_colsum(pr.W, pr.n, pr.r, h->Sp, nullptr, nullptr, h->partials, h->sum_blocks, h->stream));
+    OrderArg identity{};
+    for (int k = 0; k < pr.r; ++k) identity.ids[k] = k;
+    HIP_TRY(h, launch_permute_colsum(pr.W, pr.n, pr.r, h->Sp, identity, nullptr, nullptr, h->partials, h->sum_blocks, h->stream));
     HIP_TRY(h, launch_finalize_sums(h->partials, h->sum_blocks, pr.r, h->sums2, h->stream));
-    HIP_TRY(h, launch_permute_colsum(pr.F, pr.m, pr.r, h->Sp, nullptr, nullptr, h->partials, h->sum_blocks, h->stream));
+    HIP_TRY(h, launch_permute_colsum(pr.F, pr.m, pr.r, h->Sp, identity, nullptr, nullptr, h->partials, h->sum_blocks, h->stream));
     HIP_TRY(h, launch_finalize_sums(h->partials, h->sum_blocks, pr.r, h->sums2 + pr.r, h->stream));
-    {
+    if (carried && (h->model == kModelCsr || h->model == kModelCsc || h->model == kModelCscFresh)) {
+        const bool csr = h->model == kModelCsr;
+        const int tm = timer_begin(h, NMFKL_T_MODEL);
+        HIP_TRY(h, launch_model_terms(csr ? h->Mcsr : h->Mcsc, csr ? pr.csr_val : pr.csc_val, pr.nnz,
+                                      h->obj_partials, h->obj_blocks, h->stream));
+        timer_end(h, tm);
+    } else {
         const int rc = refresh_model(h);
         if (rc) return rc;
     }
@@ -542,6 +572,7 @@ int nmfkl_objective(nmfkl_handle* h, double* D_out) {
     *D_out = part + total;
     return NMFKL_OK;
 }
+}  // namespace
 
 int nmfkl_get_stats(nmfkl_handle* h, nmfkl_stats* out) {
     if (!h) return fail(nullptr, NMFKL_E_INVAL, "null handle");

@@ -64,6 +64,11 @@ __host__ __device__ inline void coordinate_order(uint64_t seed, uint64_t t, uint
     }
 }
 
+// A coordinate order passed by value to a kernel.
+struct OrderArg {
+    int32_t ids[NMFKL_R_MAX];
+};
+
 // One half-sweep's per-launch arguments.
 struct SweepArgs {
     const int64_t* ptr;     // segment pointers (CSC for the F-half, CSR for the W-half)
@@ -100,8 +105,8 @@ constexpr int kMaxFusedLength = 1024;   // 256 * 4
 
 // Longer segments: blocks of kLongThreads threads, kLongE nonzeros per thread; a segment
 // spans B = ceil(L / kLongCapacity) cooperating blocks.
-constexpr int kLongThreads = 1024;
-constexpr int kLongE = 4;
+constexpr int kLongThreads = 256;
+constexpr int kLongE = 8;
 constexpr int kLongCapacity = kLongThreads * kLongE;
 
 // A block of a long-segment launch.
@@ -113,18 +118,28 @@ struct LongWork {
 };
 
 // Launch wrappers (defined with the kernels).  All enqueue on `stream`.
-hipError_t launch_make_order(uint64_t seed, uint64_t t, uint64_t stream_id, int r, int32_t* ids,
-                             hipStream_t stream);
-hipError_t launch_permute_colsum(const float* A, int64_t P, int r, int Sp, const int32_t* ids,
-                                 float* Ap, double* partials, int nblocks, hipStream_t stream);
+hipError_t launch_permute_colsum(const float* A, int64_t P, int r, int Sp, const OrderArg& order,
+                                 int32_t* ids_out, float* Ap, double* partials, int nblocks,
+                                 hipStream_t stream);
+hipError_t launch_model_terms(const double* M, const float* val, int64_t nnz, double* partials,
+                              int nblocks, hipStream_t stream);
 hipError_t launch_finalize_sums(const double* partials, int nblocks, int r, double* out,
                                 hipStream_t stream);
 hipError_t launch_sweep_fused(const SweepArgs& a, const BlockWork* work, const int32_t* segs,
-                              int nblocks, hipStream_t stream);
-// Cooperative launch over long segments; zeroes the group counters first.  partials holds
-// 4 * pmax doubles per group (pmax = largest B in the launch).
+                              int nblocks, bool lookahead, hipStream_t stream);
+// Long segments that fit one block (B = 1): ordinary launch.
+hipError_t launch_sweep_long_single(const SweepArgs& a, const LongWork* work, int nblocks,
+                                    hipStream_t stream);
+// Partial sums a cooperating block publishes per reduction (S1 and S2 of every chunk
+// coordinate).
+constexpr int kCoopValues = 2 * kChunk;
+// Words per arrival flag of a cooperating block (one 128-byte line each).
+constexpr int kFlagStride = 32;
+// Cooperative launch over long segments; zeroes the arrival flags first.  partials holds
+// 2 * pmax * kCoopValues doubles and flags pmax * kFlagStride words per group (pmax =
+// largest B in the launch).
 hipError_t launch_sweep_long(const SweepArgs& a, const LongWork* work, int nblocks, double* partials,
-                             unsigned* counters, int ngroups, unsigned* err, int pmax,
+                             unsigned* flags, int ngroups, unsigned* err, int pmax,
                              hipStream_t stream);
 // Co-resident blocks of the long-segment kernel per compute unit (0 on failure).
 int long_kernel_blocks_per_cu();

@@ -54,35 +54,24 @@ __device__ __forceinline__ float group_sum(float v) {
 
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// ---------------------------------------------------------------- permutation
-__global__ void k_make_order(uint64_t seed, uint64_t t, uint64_t stream_id, int r, int32_t* ids) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        int32_t tmp[NMFKL_R_MAX];
-        coordinate_order(seed, t, stream_id, r, tmp);
-        for (int i = 0; i < r; ++i) ids[i] = tmp[i];
-    }
-}
-
-hipError_t launch_make_order(uint64_t seed, uint64_t t, uint64_t stream_id, int r, int32_t* ids,
-                             hipStream_t stream) {
-    hipLaunchKernelGGL(k_make_order, dim3(1), dim3(64), 0, stream, seed, t, stream_id, r, ids);
-    return hipGetLastError();
-}
-
 // ------------------------------------------------- permuted copy + float64 column sums
-// Block b covers rows [b*rpb, (b+1)*rpb).  Thread (ry, cx) walks rows ry, ry+4, ... of the
-// block for permuted column s = s0 + cx, reading A[p][ids[s]] and writing Ap[p][s] (zero in
-// the padding).  Per-block float64 partial sums go to partials[b*r + s]; the final sum over
-// blocks is taken in block order by k_finalize_sums, so the result is deterministic.
+// The coordinate order arrives by value (computed on the host from the same Philox
+// definition); block 0 also stores it for the sweep kernels.  Block b covers rows
+// [b*rpb, (b+1)*rpb).  Thread (ry, cx) walks rows ry, ry+4, ... of the block for permuted
+// column s = s0 + cx, reading A[p][ids[s]] and writing Ap[p][s] (zero in the padding).
+// Per-block float64 partial sums go to partials[b*r + s]; k_finalize_sums adds them in a
+// fixed order, so the result is deterministic.
 __global__ void __launch_bounds__(256) k_permute_colsum(const float* __restrict__ A, int64_t P,
-                                                        int r, int Sp,
-                                                        const int32_t* __restrict__ ids,
+                                                        int r, int Sp, OrderArg order,
+                                                        int32_t* __restrict__ ids_out,
                                                         float* __restrict__ Ap,
                                                         double* __restrict__ partials,
                                                         int64_t rpb) {
     __shared__ int32_t sid[NMFKL_R_MAX];
     __shared__ double red[4][64];
-    for (int s = threadIdx.x; s < NMFKL_R_MAX; s += 256) sid[s] = s < r ? (ids ? ids[s] : s) : -1;
+    for (int s = threadIdx.x; s < NMFKL_R_MAX; s += 256) sid[s] = s < r ? order.ids[s] : -1;
+    if (ids_out && blockIdx.x == 0)
+        for (int s = threadIdx.x; s < r; s += 256) ids_out[s] = order.ids[s];
     __syncthreads();
     const int cx = threadIdx.x & 63, ry = threadIdx.x >> 6;
     const int64_t p0 = (int64_t)blockIdx.x * rpb;
@@ -106,28 +95,35 @@ __global__ void __launch_bounds__(256) k_permute_colsum(const float* __restrict_
     }
 }
 
-hipError_t launch_permute_colsum(const float* A, int64_t P, int r, int Sp, const int32_t* ids,
-                                 float* Ap, double* partials, int nblocks, hipStream_t stream) {
+hipError_t launch_permute_colsum(const float* A, int64_t P, int r, int Sp, const OrderArg& order,
+                                 int32_t* ids_out, float* Ap, double* partials, int nblocks,
+                                 hipStream_t stream) {
     const int64_t rpb = (P + nblocks - 1) / nblocks;
-    hipLaunchKernelGGL(k_permute_colsum, dim3(nblocks), dim3(256), 0, stream, A, P, r, Sp, ids, Ap,
-                       partials, rpb);
+    hipLaunchKernelGGL(k_permute_colsum, dim3(nblocks), dim3(256), 0, stream, A, P, r, Sp, order,
+                       ids_out, Ap, partials, rpb);
     return hipGetLastError();
 }
 
-__global__ void k_finalize_sums(const double* __restrict__ partials, int nblocks, int r,
-                                double* __restrict__ out) {
-    const int s = threadIdx.x;
-    if (s < r) {
-        double acc = 0.0;
-        for (int b = 0; b < nblocks; ++b) acc += partials[(int64_t)b * r + s];
-        out[s] = acc;
+// One block per column s: the block's threads add the per-block partials b = t, t+256, ...
+// and a fixed tree combines them.
+__global__ void __launch_bounds__(256) k_finalize_sums(const double* __restrict__ partials,
+                                                       int nblocks, int r, double* __restrict__ out) {
+    __shared__ double red[256];
+    const int s = blockIdx.x;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) acc += partials[(int64_t)b * r + s];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) out[s] = red[0];
 }
 
 hipError_t launch_finalize_sums(const double* partials, int nblocks, int r, double* out,
                                 hipStream_t stream) {
-    hipLaunchKernelGGL(k_finalize_sums, dim3(1), dim3(NMFKL_R_MAX), 0, stream, partials, nblocks, r,
-                       out);
+    hipLaunchKernelGGL(k_finalize_sums, dim3(r), dim3(256), 0, stream, partials, nblocks, r, out);
     return hipGetLastError();
 }
 
@@ -140,197 +136,144 @@ struct Elems {
     float v[E], w[E], u[E];
 };
 
-// ---- segment-wide all-reduce of (S1, S2): three reducers with one interface -----------
-// Every lane of a segment receives bit-identical sums, so every lane takes the same Newton
-// decisions.
+// ---- segment-wide all-reduce of NV partial sums ----------------------------------------
+// sum(v, lo) all-reduces v[lo..NV) over the lanes of a segment.  Every lane of a segment
+// receives bit-identical sums, so every lane takes the same Newton decisions.  lo is a
+// compile-time constant after unrolling at every call site.
 
 // Segments of G <= 64 lanes inside one wave: DPP / lane shuffles only.
 template <int G>
 struct WaveReducer {
-    __device__ __forceinline__ float2 sum(float2 s) {
-        s.x = group_sum<G>(s.x);
-        s.y = group_sum<G>(s.y);
-        return s;
+    template <int NV>
+    __device__ __forceinline__ void sum(float (&v)[NV], int lo) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+            if (i >= lo) v[i] = group_sum<G>(v[i]);
     }
 };
 
 // One segment per block of NT threads: wave sums, then the NT/64 wave sums through LDS in
-// wave order (double-buffered by parity, one barrier per reduction).
+// wave order (double-buffered by parity: one barrier per reduction).  red holds
+// 2 * (NT/64) * kMaxRed floats.
+constexpr int kMaxRed = kCoopValues;
+
 template <int NT>
 struct BlockReducer {
-    float2* red;  // LDS, 2 * NT/64 entries
+    float* red;
     int parity;
-    __device__ __forceinline__ float2 sum(float2 s) {
-        s.x = group_sum<64>(s.x);
-        s.y = group_sum<64>(s.y);
+    template <int NV>
+    __device__ __forceinline__ void sum(float (&v)[NV], int lo) {
         constexpr int W = NT / 64;
-        const int wv = threadIdx.x >> 6;
-        if ((threadIdx.x & 63) == 0) red[parity * W + wv] = s;
-        __syncthreads();
-        float2 t = red[parity * W];
 #pragma unroll
-        for (int q = 1; q < W; ++q) {
-            t.x += red[parity * W + q].x;
-            t.y += red[parity * W + q].y;
+        for (int i = 0; i < NV; ++i)
+            if (i >= lo) v[i] = group_sum<64>(v[i]);
+        const int wv = threadIdx.x >> 6;
+        float* mine = red + (parity * W + wv) * kMaxRed;
+        if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i)
+                if (i >= lo) mine[i] = v[i];
+        }
+        __syncthreads();
+        const float* base = red + parity * W * kMaxRed;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            if (i >= lo) {
+                float t = base[i];
+#pragma unroll
+                for (int q = 1; q < W; ++q) t += base[q * kMaxRed + i];
+                v[i] = t;
+            }
         }
         parity ^= 1;
-        return t;
     }
 };
 
 // A long segment split over B co-resident blocks (cooperative launch).  Each reduction:
-// block sum; thread 0 publishes it (float64) in slot parity of the group's partials and
-// arrives on the group's counter with release semantics, then waits (acquire) until all B
-// blocks arrived; wave 0 reads the B partials, lane b holding partials b, b+64, ..., and
-// all-reduces them with a fixed butterfly, so every block obtains the same total.  The wait
-// is bounded: after kSpinLimit polls, or as soon as any block has recorded an error, the
+// block sum; lanes i < NV publish partial i (float64) into slot `round & 1` of the group's
+// partials with coherent atomic stores; once they are performed, thread 0 stores the
+// block's round number in its own flag line.  Wave 0 then polls the B flags in parallel (no
+// shared counter: same-address atomics from many blocks serialise at the coherence point)
+// until every block has published this round.  All threads read the partials, thread
+// (i, j) adding partial i of blocks j, j+16, ..., and thread i < NV adds the 16 results in
+// order, so every block obtains the same totals.  Every shared access is an atomic
+// performed at the device coherence point, so no cache-maintaining fence is needed.  The
+// wait is bounded: after kSpinLimit polls, or once any block has recorded an error, the
 // block records an error and continues (the host reports it at the next synchronising call).
 constexpr unsigned kSpinLimit = 1u << 20;
 
-__device__ __forceinline__ double shfl_xor_f64(double v, int m) {
-    int2 p = *reinterpret_cast<int2*>(&v);
-    p.x = __shfl_xor(p.x, m);
-    p.y = __shfl_xor(p.y, m);
-    return *reinterpret_cast<double*>(&p);
-}
-
 template <int NT>
 struct CoopReducer {
+    static_assert(NT == 16 * kMaxRed, "the partial read uses NT / kMaxRed lanes per value");
     BlockReducer<NT> blk;
-    double* bcast;      // LDS, 2 doubles
-    double* partials;   // global: [2][B][2] for this group
-    unsigned* counter;  // global: arrivals of this group
+    double* tmp;        // LDS, 16 * kMaxRed doubles
+    double* bcast;      // LDS, kMaxRed doubles
+    double* partials;   // global: [2][B][kMaxRed] for this group
+    unsigned* flags;    // global: B flag lines of kFlagStride words for this group
     unsigned* err;      // global error flags
     int B, part;
     unsigned round;
-    __device__ __forceinline__ float2 sum(float2 s) {
-        const float2 b = blk.sum(s);
-        if (B == 1) return b;
+    template <int NV>
+    __device__ __forceinline__ void sum(float (&v)[NV], int lo) {
+        blk.sum(v, lo);
+        if (B == 1) return;
         const unsigned slot = round & 1u;
-        if (threadIdx.x == 0) {
-            double* p = partials + ((size_t)slot * B + part) * 2;
-            __hip_atomic_store(p, (double)b.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(p + 1, (double)b.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            const unsigned target = (round + 1u) * (unsigned)B;
+        const int tid = threadIdx.x;
+        if (tid >= lo && tid < NV) {
+            float mine = 0.0f;
+#pragma unroll
+            for (int i = 0; i < NV; ++i)
+                if (i == tid) mine = v[i];
+            unsigned long long* p = reinterpret_cast<unsigned long long*>(partials) +
+                                    ((size_t)slot * B + part) * kMaxRed + tid;
+            __hip_atomic_store(p, (unsigned long long)__double_as_longlong((double)mine),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (tid < 64) {
+            // the partial stores of this wave have been performed before the flag is raised
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            if (tid == 0)
+                __hip_atomic_store(flags + (size_t)part * kFlagStride, round + 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
             unsigned spins = 0;
-            while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            for (;;) {
+                bool ok = true;
+                for (int b = tid; b < B; b += 64)
+                    ok &= __hip_atomic_load(flags + (size_t)b * kFlagStride, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT) >= round + 1u;
+                if (__all(ok)) break;
                 __builtin_amdgcn_s_sleep(1);
-                // give up on a timeout, or at once once any block has given up
                 if (++spins > kSpinLimit ||
                     __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                    atomicOr(err, 1u);
+                    if (tid == 0) atomicOr(err, 1u);
                     break;
                 }
             }
         }
         __syncthreads();
-        if (threadIdx.x < 64) {
-            double sx = 0.0, sy = 0.0;
-            for (int q = threadIdx.x; q < B; q += 64) {
-                const double* p = partials + ((size_t)slot * B + q) * 2;
-                sx += __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                sy += __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        {
+            const int i = tid % kMaxRed, j = tid / kMaxRed;
+            double acc = 0.0;
+            if (i >= lo && i < NV) {
+                const double* q = partials + (size_t)slot * B * kMaxRed + i;
+                for (int b = j; b < B; b += NT / kMaxRed)
+                    acc += __hip_atomic_load(q + (size_t)b * kMaxRed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-#pragma unroll
-            for (int m = 1; m < 64; m <<= 1) {
-                sx += shfl_xor_f64(sx, m);
-                sy += shfl_xor_f64(sy, m);
-            }
-            if (threadIdx.x == 0) {
-                bcast[0] = sx;
-                bcast[1] = sy;
-            }
+            tmp[j * kMaxRed + i] = acc;
         }
         __syncthreads();
+        if (tid >= lo && tid < NV) {
+            double acc = 0.0;
+            for (int j = 0; j < NT / kMaxRed; ++j) acc += tmp[j * kMaxRed + tid];
+            bcast[tid] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+            if (i >= lo) v[i] = (float)bcast[i];
         ++round;
-        return make_float2((float)bcast[0], (float)bcast[1]);
     }
 };
-
-// Alg. 2's inner loop for one coordinate s of one segment.  tk[e] holds A[i_l][s] for the
-// lane's nonzeros.  xs points at the segment's x in LDS (permuted order).
-template <int E, class Red>
-__device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s, const float (&tk)[E],
-                                                Elems<E>& st, float* xs, Red& red,
-                                                unsigned (&cnt)[6]) {
-    float xk = xs[s];
-    const double sA = a.sumA[s];
-    float2 acc = make_float2(0.0f, 0.0f);
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        acc.x = fmaf(tk[e], st.w[e], acc.x);
-        acc.y = fmaf(tk[e] * tk[e], st.u[e], acc.y);
-    }
-    acc = red.sum(acc);
-    double P = sA + (double)a.alpha * xk + (double)a.beta;
-    double g = P - (double)acc.x;
-    float h = acc.y + a.alpha;
-    cnt[0] += 1;
-    cnt[1] += 1;
-    int steps = 0;
-    while ((g < -(double)a.eps_g * P) || (g > (double)a.eps_g * P && xk > 0.0f)) {
-        float d;
-        if (h <= 0.0f) {
-            if (g > 0.0) d = -xk;
-            else break;
-        } else {
-            const float xn = xk - (float)g / h;
-            d = fmaxf(xn, 0.0f) - xk;
-        }
-        const float dN = d;  // Alg. 2's projected Newton step (the break test uses it)
-        double mm[E];
-        float wn[E], un[E];
-        double gn, Pn;
-        float hn;
-        int j = 0;
-        bool rejected = false;
-        for (;;) {
-            float2 t2 = make_float2(0.0f, 0.0f);
-            const double dd = (double)d;
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const double m = fmax(fma(dd, (double)tk[e], st.ax[e]), 0.0);
-                const float ri = fast_rcp((float)m + a.eps_log);
-                const float ww = st.v[e] * ri;
-                mm[e] = m;
-                wn[e] = ww;
-                un[e] = ww * ri;
-                t2.x = fmaf(tk[e], ww, t2.x);
-                t2.y = fmaf(tk[e] * tk[e], un[e], t2.y);
-            }
-            t2 = red.sum(t2);
-            cnt[1] += 1;
-            const float xt = xk + d;
-            Pn = sA + (double)a.alpha * xt + (double)a.beta;
-            gn = Pn - (double)t2.x;
-            hn = t2.y + a.alpha;
-            if (!(a.guard && d < 0.0f && g + gn < 0.0)) break;
-            if (j == a.j_max) { rejected = true; break; }
-            d *= 0.5f;
-            ++j;
-            cnt[3] += 1;
-        }
-        if (rejected) { cnt[4] += 1; break; }
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            st.ax[e] = mm[e];
-            st.w[e] = wn[e];
-            st.u[e] = un[e];
-        }
-        const float xprev = xk;
-        xk = xk + d;
-        g = gn;
-        h = hn;
-        P = Pn;
-        ++steps;
-        cnt[2] += 1;
-        const bool stop = a.literal_break ? (dN < a.eps_x * xprev) : (fabsf(dN) < a.eps_x * xprev);
-        if (stop) break;
-        if (steps >= a.t_max) { cnt[5] += 1; break; }
-    }
-    xs[s] = xk;
-}
 
 // Elements handled by this lane: l = lo + lane + STRIDE * e, e < E, restricted to l < L.
 template <int E, int STRIDE>
@@ -360,9 +303,152 @@ __device__ __forceinline__ float comp(const float4 (&t)[E][2], int e, int cc) {
     }
 }
 
+// Alg. 2's inner loop for coordinate s = c*kChunk + cc of one segment.  t holds the chunk's
+// fixed-factor values for the lane's nonzeros, xs the segment's x in LDS (permuted order).
+// LA (lookahead): LS[2k], LS[2k+1] hold eq. 6's sums S1, S2 of chunk coordinate k >= cc at
+// the current model; every trial evaluation also computes the sums of the chunk
+// coordinates after cc at the trial model, so that an accepted step leaves LS valid.  The
+// sums are the same numbers the sequential order would compute later from the same model.
+// Without LA, the coordinate's own sums are evaluated here.
+template <int cc, int E, bool LA, class Red>
+__device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s,
+                                                const float4 (&t)[E][2], Elems<E>& st, float* xs,
+                                                Red& red, float (&LS)[kMaxRed], unsigned (&cnt)[6]) {
+    float xk = xs[s];
+    const double sA = a.sumA[s];
+    float tk[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) tk[e] = comp<E>(t, e, cc);
+    float S1, S2;
+    if constexpr (LA) {
+        S1 = LS[2 * cc];
+        S2 = LS[2 * cc + 1];
+    } else {
+        float acc[2] = {0.0f, 0.0f};
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            acc[0] = fmaf(tk[e], st.w[e], acc[0]);
+            acc[1] = fmaf(tk[e] * tk[e], st.u[e], acc[1]);
+        }
+        red.sum(acc, 0);
+        S1 = acc[0];
+        S2 = acc[1];
+        cnt[1] += 1;
+    }
+    double P = sA + (double)a.alpha * xk + (double)a.beta;
+    double g = P - (double)S1;
+    float h = S2 + a.alpha;
+    cnt[0] += 1;
+    int steps = 0;
+    while ((g < -(double)a.eps_g * P) || (g > (double)a.eps_g * P && xk > 0.0f)) {
+        float d;
+        if (h <= 0.0f) {
+            if (g > 0.0) d = -xk;
+            else break;
+        } else {
+            const float xn = xk - (float)g / h;
+            d = fmaxf(xn, 0.0f) - xk;
+        }
+        const float dN = d;  // Alg. 2's projected Newton step (the break test uses it)
+        double mm[E];
+        float wn[E], un[E];
+        float acc[kMaxRed];
+        double gn, Pn;
+        float hn;
+        int j = 0;
+        bool rejected = false;
+        for (;;) {
+#pragma unroll
+            for (int i = 0; i < kMaxRed; ++i) acc[i] = 0.0f;
+            const double dd = (double)d;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const double m = fmax(fma(dd, (double)tk[e], st.ax[e]), 0.0);
+                const float ri = fast_rcp((float)m + a.eps_log);
+                const float ww = st.v[e] * ri;
+                const float uu = ww * ri;
+                mm[e] = m;
+                wn[e] = ww;
+                un[e] = uu;
+                acc[2 * cc] = fmaf(tk[e], ww, acc[2 * cc]);
+                acc[2 * cc + 1] = fmaf(tk[e] * tk[e], uu, acc[2 * cc + 1]);
+                if constexpr (LA) {
+#pragma unroll
+                    for (int k = 0; k < kChunk; ++k) {
+                        if (k > cc) {
+                            const float tq = comp<E>(t, e, k);
+                            acc[2 * k] = fmaf(tq, ww, acc[2 * k]);
+                            acc[2 * k + 1] = fmaf(tq * tq, uu, acc[2 * k + 1]);
+                        }
+                    }
+                }
+            }
+            if constexpr (LA) {
+                red.sum(acc, 2 * cc);
+            } else {
+                float two[2] = {acc[2 * cc], acc[2 * cc + 1]};
+                red.sum(two, 0);
+                acc[2 * cc] = two[0];
+                acc[2 * cc + 1] = two[1];
+            }
+            cnt[1] += 1;
+            const float xt = xk + d;
+            Pn = sA + (double)a.alpha * xt + (double)a.beta;
+            gn = Pn - (double)acc[2 * cc];
+            hn = acc[2 * cc + 1] + a.alpha;
+            if (!(a.guard && d < 0.0f && g + gn < 0.0)) break;
+            if (j == a.j_max) { rejected = true; break; }
+            d *= 0.5f;
+            ++j;
+            cnt[3] += 1;
+        }
+        if (rejected) { cnt[4] += 1; break; }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            st.ax[e] = mm[e];
+            st.w[e] = wn[e];
+            st.u[e] = un[e];
+        }
+        if constexpr (LA) {
+#pragma unroll
+            for (int k = 0; k < kChunk; ++k)
+                if (k > cc) {
+                    LS[2 * k] = acc[2 * k];
+                    LS[2 * k + 1] = acc[2 * k + 1];
+                }
+        }
+        const float xprev = xk;
+        xk = xk + d;
+        g = gn;
+        h = hn;
+        P = Pn;
+        ++steps;
+        cnt[2] += 1;
+        const bool stop = a.literal_break ? (dN < a.eps_x * xprev) : (fabsf(dN) < a.eps_x * xprev);
+        if (stop) break;
+        if (steps >= a.t_max) { cnt[5] += 1; break; }
+    }
+    xs[s] = xk;
+}
+
+// The coordinates of chunk c in order (template recursion: each coordinate index is a
+// compile-time constant, so every register array is indexed statically).
+template <int CC, int E, bool LA, class Red>
+__device__ __forceinline__ void chunk_steps(const SweepArgs& a, int c, const float4 (&t)[E][2],
+                                            Elems<E>& st, float* xs, Red& red, float (&LS)[kMaxRed],
+                                            unsigned (&cnt)[6]) {
+    if constexpr (CC < kChunk) {
+        const int s = c * kChunk + CC;
+        if (s < a.r) {
+            coordinate_step<CC, E, LA>(a, s, t, st, xs, red, LS, cnt);
+            chunk_steps<CC + 1, E, LA>(a, c, t, st, xs, red, LS, cnt);
+        }
+    }
+}
+
 // Alg. 2 on one segment (or on this block's part [lo, lo + STRIDE*E) of a long segment).
-// PREFETCH: keep the next tile chunk in flight while the current one is processed.
-template <int STRIDE, int E, bool PREFETCH, class Red>
+// PREFETCH keeps the next tile chunk in flight while the current one is processed.
+template <int STRIDE, int E, bool PREFETCH, bool LA, class Red>
 __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool active, int lane,
                                               int lo, bool count_stats, float* xs, Red& red) {
     int64_t base = 0;
@@ -397,16 +483,24 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool 
     for (int c = 0; c < nchunks; ++c) {
         float4 nxt[E][2];
         if (PREFETCH && c + 1 < nchunks) load_chunk<E, STRIDE>(a, st, L, lo, lane, c + 1, nxt);
+        float LS[kMaxRed];
+        if constexpr (LA) {
+            // eq. 6's sums of every coordinate of the chunk at the current model
 #pragma unroll
-        for (int cc = 0; cc < kChunk; ++cc) {
-            const int s = c * kChunk + cc;
-            if (s < a.r) {
-                float tk[E];
+            for (int i = 0; i < kMaxRed; ++i) LS[i] = 0.0f;
 #pragma unroll
-                for (int e = 0; e < E; ++e) tk[e] = comp<E>(cur, e, cc);
-                coordinate_step<E>(a, s, tk, st, xs, red, cnt);
+            for (int e = 0; e < E; ++e) {
+#pragma unroll
+                for (int k = 0; k < kChunk; ++k) {
+                    const float tq = comp<E>(cur, e, k);
+                    LS[2 * k] = fmaf(tq, st.w[e], LS[2 * k]);
+                    LS[2 * k + 1] = fmaf(tq * tq, st.u[e], LS[2 * k + 1]);
+                }
             }
+            red.sum(LS, 0);
+            cnt[1] += 1;
         }
+        chunk_steps<0, E, LA>(a, c, cur, st, xs, red, LS, cnt);
         if (PREFETCH) {
 #pragma unroll
             for (int e = 0; e < E; ++e) {
@@ -429,9 +523,9 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool 
     }
 }
 
-template <int G, int E>
+template <int G, int E, bool LA>
 __device__ __forceinline__ void sweep_block(const SweepArgs& a, const BlockWork& wk, const int32_t* segs,
-                                            float* xs_all, float2* red_lds) {
+                                            float* xs_all, float* red_lds) {
     const int slot = threadIdx.x / G;
     const int lane = threadIdx.x % G;
     const bool active = slot < wk.count;
@@ -443,10 +537,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const BlockWork&
     __syncthreads();
     if constexpr (G <= 64) {
         WaveReducer<G> red;
-        sweep_segment<G, E, true>(a, seg, active, lane, 0, true, xs, red);
+        sweep_segment<G, E, true, LA>(a, seg, active, lane, 0, true, xs, red);
     } else {
         BlockReducer<G> red{red_lds, 0};
-        sweep_segment<G, E, true>(a, seg, active, lane, 0, true, xs, red);
+        sweep_segment<G, E, true, LA>(a, seg, active, lane, 0, true, xs, red);
         __syncthreads();
     }
     if (active)
@@ -454,52 +548,67 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const BlockWork&
 }
 
 // The fused binned launch: each block picks its (G, E) variant from the work table.
+// LA256 selects the lookahead form for the 256-lane variant.
+template <bool LA256>
 __global__ void __launch_bounds__(kFusedThreads, 2)
 k_sweep_fused(SweepArgs a, const BlockWork* __restrict__ work, const int32_t* __restrict__ segs) {
     __shared__ float xs_all[(kFusedThreads / 8) * NMFKL_R_MAX];
-    __shared__ float2 red[2 * (kFusedThreads / 64)];
+    __shared__ float red[2 * (kFusedThreads / 64) * kMaxRed];
     const BlockWork wk = work[blockIdx.x];
     switch (wk.variant) {
-        case 0: sweep_block<8, 4>(a, wk, segs, xs_all, red); break;
-        case 1: sweep_block<16, 4>(a, wk, segs, xs_all, red); break;
-        case 2: sweep_block<32, 4>(a, wk, segs, xs_all, red); break;
-        case 3: sweep_block<64, 4>(a, wk, segs, xs_all, red); break;
-        default: sweep_block<256, 4>(a, wk, segs, xs_all, red); break;
+        case 0: sweep_block<8, 4, false>(a, wk, segs, xs_all, red); break;
+        case 1: sweep_block<16, 4, false>(a, wk, segs, xs_all, red); break;
+        case 2: sweep_block<32, 4, false>(a, wk, segs, xs_all, red); break;
+        case 3: sweep_block<64, 4, false>(a, wk, segs, xs_all, red); break;
+        default: sweep_block<256, 4, LA256>(a, wk, segs, xs_all, red); break;
     }
 }
 
 hipError_t launch_sweep_fused(const SweepArgs& a, const BlockWork* work, const int32_t* segs,
-                              int nblocks, hipStream_t stream) {
+                              int nblocks, bool lookahead, hipStream_t stream) {
     if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sweep_fused, dim3(nblocks), dim3(kFusedThreads), 0, stream, a, work, segs);
+    if (lookahead)
+        hipLaunchKernelGGL(k_sweep_fused<true>, dim3(nblocks), dim3(kFusedThreads), 0, stream, a, work, segs);
+    else
+        hipLaunchKernelGGL(k_sweep_fused<false>, dim3(nblocks), dim3(kFusedThreads), 0, stream, a, work, segs);
     return hipGetLastError();
 }
 
-// Long segments: kLongThreads threads x kLongE elements per block; a segment of L nonzeros
-// takes B = ceil(L / (kLongThreads*kLongE)) blocks that cooperate through CoopReducer.  All
-// blocks of one launch are co-resident (cooperative launch), so every wait ends.
+// Long segments: kLongThreads threads x kLongE nonzeros per block, lookahead form.  A
+// segment of L nonzeros takes B = ceil(L / kLongCapacity) blocks.  COOP = false: one block
+// per segment (B = 1), ordinary launch.  COOP = true: the blocks of a segment cooperate
+// through CoopReducer; all blocks of the launch are co-resident (cooperative launch), so
+// every wait ends.
+template <bool COOP>
 __global__ void __launch_bounds__(kLongThreads)
 k_sweep_long(SweepArgs a, const LongWork* __restrict__ work, double* __restrict__ partials,
-             unsigned* __restrict__ counters, unsigned* __restrict__ err, int pmax) {
+             unsigned* __restrict__ flags, unsigned* __restrict__ err, int pmax) {
     __shared__ float xs[NMFKL_R_MAX];
-    __shared__ float2 red_lds[2 * (kLongThreads / 64)];
-    __shared__ double bcast[2];
+    __shared__ float red_lds[2 * (kLongThreads / 64) * kMaxRed];
+    __shared__ double tmp[(kLongThreads / kMaxRed) * kMaxRed];
+    __shared__ double bcast[kMaxRed];
     const LongWork wk = work[blockIdx.x];
     const int lane = threadIdx.x;
     for (int s = lane; s < a.r; s += kLongThreads) xs[s] = a.X[(int64_t)wk.seg * a.r + a.ids[s]];
     __syncthreads();
-    CoopReducer<kLongThreads> red;
-    red.blk.red = red_lds;
-    red.blk.parity = 0;
-    red.bcast = bcast;
-    red.partials = partials + (size_t)wk.group * 2 * 2 * pmax;
-    red.counter = counters + wk.group;
-    red.err = err;
-    red.B = wk.B;
-    red.part = wk.part;
-    red.round = 0;
-    sweep_segment<kLongThreads, kLongE, false>(a, wk.seg, true, lane, wk.part * kLongThreads * kLongE,
-                                               wk.part == 0, xs, red);
+    if constexpr (COOP) {
+        CoopReducer<kLongThreads> red;
+        red.blk.red = red_lds;
+        red.blk.parity = 0;
+        red.tmp = tmp;
+        red.bcast = bcast;
+        red.partials = partials + (size_t)wk.group * 2 * pmax * kMaxRed;
+        red.flags = flags + (size_t)wk.group * pmax * kFlagStride;
+        red.err = err;
+        red.B = wk.B;
+        red.part = wk.part;
+        red.round = 0;
+        sweep_segment<kLongThreads, kLongE, false, true>(a, wk.seg, true, lane,
+                                                         wk.part * kLongCapacity, wk.part == 0, xs, red);
+    } else {
+        BlockReducer<kLongThreads> red{red_lds, 0};
+        sweep_segment<kLongThreads, kLongE, false, true>(a, wk.seg, true, lane, 0, true, xs, red);
+    }
     __syncthreads();
     if (wk.part == 0)
         for (int s = lane; s < a.r; s += kLongThreads) a.X[(int64_t)wk.seg * a.r + a.ids[s]] = xs[s];
@@ -510,22 +619,31 @@ __global__ void k_zero_u32(unsigned* p, int n) {
     if (i < n) p[i] = 0u;
 }
 
+hipError_t launch_sweep_long_single(const SweepArgs& a, const LongWork* work, int nblocks,
+                                    hipStream_t stream) {
+    if (nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sweep_long<false>, dim3(nblocks), dim3(kLongThreads), 0, stream, a, work,
+                       (double*)nullptr, (unsigned*)nullptr, (unsigned*)nullptr, 0);
+    return hipGetLastError();
+}
+
 hipError_t launch_sweep_long(const SweepArgs& a, const LongWork* work, int nblocks, double* partials,
-                             unsigned* counters, int ngroups, unsigned* err, int pmax,
+                             unsigned* flags, int ngroups, unsigned* err, int pmax,
                              hipStream_t stream) {
     if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zero_u32, dim3((ngroups + 255) / 256), dim3(256), 0, stream, counters, ngroups);
+    const int nflags = ngroups * pmax * kFlagStride;
+    hipLaunchKernelGGL(k_zero_u32, dim3((nflags + 255) / 256), dim3(256), 0, stream, flags, nflags);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     SweepArgs aa = a;
-    void* args[] = {&aa, &work, &partials, &counters, &err, &pmax};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_sweep_long), dim3(nblocks),
+    void* args[] = {&aa, &work, &partials, &flags, &err, &pmax};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_sweep_long<true>), dim3(nblocks),
                                       dim3(kLongThreads), args, 0, stream);
 }
 
 int long_kernel_blocks_per_cu() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_sweep_long),
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_sweep_long<true>),
                                                      kLongThreads, 0) != hipSuccess)
         return 0;
     return nb;
@@ -580,6 +698,32 @@ hipError_t launch_model_objective(const int64_t* csc_ptr, const int32_t* csc_idx
     const int cpb = (m + nblocks - 1) / nblocks;
     hipLaunchKernelGGL(k_model_objective, dim3(nblocks), dim3(256), 0, stream, csc_ptr, csc_idx,
                        csc_val, m, W, F, r, Mcsc, partials, cpb);
+    return hipGetLastError();
+}
+
+// eq. 1's per-nonzero terms v log(v/M) - v from model values already at hand (float64),
+// block partials to partials[blockIdx].
+__global__ void __launch_bounds__(256) k_model_terms(const double* __restrict__ M,
+                                                     const float* __restrict__ val, int64_t nnz,
+                                                     double* __restrict__ partials) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nnz; q += (int64_t)gridDim.x * 256) {
+        const float v = val[q];
+        if (v != 0.0f) acc += (double)v * log((double)v / M[q]) - (double)v;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+hipError_t launch_model_terms(const double* M, const float* val, int64_t nnz, double* partials,
+                              int nblocks, hipStream_t stream) {
+    hipLaunchKernelGGL(k_model_terms, dim3(nblocks), dim3(256), 0, stream, M, val, nnz, partials);
     return hipGetLastError();
 }
 

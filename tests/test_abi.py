@@ -37,7 +37,7 @@ def test_params_default():
     p = P.nmfkl_params_default()
     assert (p.eps_x, p.t_max, p.j_max, p.guard, p.literal_break) == (0.1, 16, 8, 1, 0)
     assert p.eps_log == 1e-10 and p.eps_g == 1e-5 and p.foldin_max_passes == 200
-    assert p.refresh_model == 1 and p.collect_stats == 0
+    assert p.refresh_model == 0 and p.collect_stats == 0 and p.collect_timings == 0
 
 
 def test_permutation_matches_oracle_and_numpy_stream(orc):

@@ -271,3 +271,28 @@ def test_sampled_parity_full_size_corpus(corpus_full):
     print(f"full corpus sampled: F rel {eF:.2e} (3000 cols), W rel {eW:.2e} ({rows.size} rows), "
           f"20 heaviest rows rel {eH:.2e}; flips F {flips(Fg[cols], Fo)} W {flips(Wg[rows], Wo)}")
     assert eF <= 1e-4 and eW <= 1e-4 and eH <= 1e-4
+
+
+def test_carried_objective_and_refresh_mode():
+    """The objective from the carried model values matches the exact one, and the
+    refresh-every-sweep mode follows the same trajectory."""
+    prob = CASES["corpus_mid"]()
+    sweeps = 6
+    res = {}
+    for refresh in (0, 1):
+        dev = P.upload(prob, "cuda")
+        h = P.nmfkl_create(dev, P.nmfkl_params_default(refresh_model=refresh))
+        Dc, De = [], []
+        for t in range(sweeps):
+            P.nmfkl_sweep_F(h, t)
+            P.nmfkl_sweep_W(h, t)
+            Dc.append(P.nmfkl_objective_carried(h))
+            De.append(P.nmfkl_objective(h))
+        res[refresh] = (np.array(Dc), np.array(De), dev.W.cpu().numpy(), dev.F.cpu().numpy())
+        P.nmfkl_destroy(h)
+    for refresh, (Dc, De, W, F) in res.items():
+        assert np.all(np.abs(Dc - De) / De <= 1e-6), (refresh, Dc, De)
+    Wo, Fo, Do = oracle.run(prob, sweeps)
+    for refresh, (Dc, De, W, F) in res.items():
+        assert np.all(np.abs(De - Do) / Do <= 1e-5)
+        assert relf(W, Wo) <= 1e-4 and relf(F, Fo) <= 1e-4
