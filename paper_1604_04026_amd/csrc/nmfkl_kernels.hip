@@ -129,11 +129,32 @@ hipError_t launch_finalize_sums(const double* partials, int nblocks, int r, doub
 
 // --------------------------------------------------------------- the sweep
 // Per-segment element state held in registers.
+// Per-nonzero state of a lane's E nonzeros: the model ax (float64, registers) and the
+// count v, w = v/(ax+eps), u = w/(ax+eps) and the point id, either in registers
+// (RegElems) or in LDS slots e*STRIDE + lane of the block (LdsElems, for the long-segment
+// kernel, whose register budget holds the tile and the model of more nonzeros that way).
 template <int E>
-struct Elems {
-    int32_t id[E];
+struct RegElems {
+    static constexpr int kE = E;
     double ax[E];
-    float v[E], w[E], u[E];
+    int32_t id_[E];
+    float v_[E], w_[E], u_[E];
+    __device__ __forceinline__ int32_t& id(int e) { return id_[e]; }
+    __device__ __forceinline__ float& v(int e) { return v_[e]; }
+    __device__ __forceinline__ float& w(int e) { return w_[e]; }
+    __device__ __forceinline__ float& u(int e) { return u_[e]; }
+};
+
+template <int E, int STRIDE>
+struct LdsElems {
+    static constexpr int kE = E;
+    double ax[E];
+    int32_t* idp;
+    float *vp, *wp, *up;
+    __device__ __forceinline__ int32_t& id(int e) { return idp[e * STRIDE]; }
+    __device__ __forceinline__ float& v(int e) { return vp[e * STRIDE]; }
+    __device__ __forceinline__ float& w(int e) { return wp[e * STRIDE]; }
+    __device__ __forceinline__ float& u(int e) { return up[e * STRIDE]; }
 };
 
 // ---- segment-wide all-reduce of NV partial sums ----------------------------------------
@@ -276,13 +297,13 @@ struct CoopReducer {
 };
 
 // Elements handled by this lane: l = lo + lane + STRIDE * e, e < E, restricted to l < L.
-template <int E, int STRIDE>
-__device__ __forceinline__ void load_chunk(const SweepArgs& a, const Elems<E>& st, int L, int lo,
+template <int E, int STRIDE, class St>
+__device__ __forceinline__ void load_chunk(const SweepArgs& a, St& st, int L, int lo,
                                            int lane, int c, float4 (&t)[E][2]) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         if (lo + lane + STRIDE * e < L) {
-            const float4* p = reinterpret_cast<const float4*>(a.Ap + (int64_t)st.id[e] * a.Sp + c * kChunk);
+            const float4* p = reinterpret_cast<const float4*>(a.Ap + (int64_t)st.id(e) * a.Sp + c * kChunk);
             t[e][0] = p[0];
             t[e][1] = p[1];
         } else {
@@ -310,9 +331,9 @@ __device__ __forceinline__ float comp(const float4 (&t)[E][2], int e, int cc) {
 // coordinates after cc at the trial model, so that an accepted step leaves LS valid.  The
 // sums are the same numbers the sequential order would compute later from the same model.
 // Without LA, the coordinate's own sums are evaluated here.
-template <int cc, int E, bool LA, class Red>
+template <int cc, int E, bool LA, class Red, class St>
 __device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s,
-                                                const float4 (&t)[E][2], Elems<E>& st, float* xs,
+                                                const float4 (&t)[E][2], St& st, float* xs,
                                                 Red& red, float (&LS)[kMaxRed], unsigned (&cnt)[6]) {
     float xk = xs[s];
     const double sA = a.sumA[s];
@@ -327,8 +348,8 @@ __device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s,
         float acc[2] = {0.0f, 0.0f};
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            acc[0] = fmaf(tk[e], st.w[e], acc[0]);
-            acc[1] = fmaf(tk[e] * tk[e], st.u[e], acc[1]);
+            acc[0] = fmaf(tk[e], st.w(e), acc[0]);
+            acc[1] = fmaf(tk[e], tk[e] * st.u(e), acc[1]);
         }
         red.sum(acc, 0);
         S1 = acc[0];
@@ -365,20 +386,20 @@ __device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s,
             for (int e = 0; e < E; ++e) {
                 const double m = fmax(fma(dd, (double)tk[e], st.ax[e]), 0.0);
                 const float ri = fast_rcp((float)m + a.eps_log);
-                const float ww = st.v[e] * ri;
+                const float ww = st.v(e) * ri;
                 const float uu = ww * ri;
                 mm[e] = m;
                 wn[e] = ww;
                 un[e] = uu;
                 acc[2 * cc] = fmaf(tk[e], ww, acc[2 * cc]);
-                acc[2 * cc + 1] = fmaf(tk[e] * tk[e], uu, acc[2 * cc + 1]);
+                acc[2 * cc + 1] = fmaf(tk[e], tk[e] * uu, acc[2 * cc + 1]);
                 if constexpr (LA) {
 #pragma unroll
                     for (int k = 0; k < kChunk; ++k) {
                         if (k > cc) {
                             const float tq = comp<E>(t, e, k);
                             acc[2 * k] = fmaf(tq, ww, acc[2 * k]);
-                            acc[2 * k + 1] = fmaf(tq * tq, uu, acc[2 * k + 1]);
+                            acc[2 * k + 1] = fmaf(tq, tq * uu, acc[2 * k + 1]);
                         }
                     }
                 }
@@ -406,8 +427,8 @@ __device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s,
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             st.ax[e] = mm[e];
-            st.w[e] = wn[e];
-            st.u[e] = un[e];
+            st.w(e) = wn[e];
+            st.u(e) = un[e];
         }
         if constexpr (LA) {
 #pragma unroll
@@ -433,9 +454,9 @@ __device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s,
 
 // The coordinates of chunk c in order (template recursion: each coordinate index is a
 // compile-time constant, so every register array is indexed statically).
-template <int CC, int E, bool LA, class Red>
+template <int CC, int E, bool LA, class Red, class St>
 __device__ __forceinline__ void chunk_steps(const SweepArgs& a, int c, const float4 (&t)[E][2],
-                                            Elems<E>& st, float* xs, Red& red, float (&LS)[kMaxRed],
+                                            St& st, float* xs, Red& red, float (&LS)[kMaxRed],
                                             unsigned (&cnt)[6]) {
     if constexpr (CC < kChunk) {
         const int s = c * kChunk + CC;
@@ -448,32 +469,33 @@ __device__ __forceinline__ void chunk_steps(const SweepArgs& a, int c, const flo
 
 // Alg. 2 on one segment (or on this block's part [lo, lo + STRIDE*E) of a long segment).
 // PREFETCH keeps the next tile chunk in flight while the current one is processed.
-template <int STRIDE, int E, bool PREFETCH, bool LA, class Red>
+template <int STRIDE, bool PREFETCH, bool LA, class Red, class St>
 __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool active, int lane,
-                                              int lo, bool count_stats, float* xs, Red& red) {
+                                              int lo, bool count_stats, float* xs, Red& red, St& st) {
+    constexpr int E = St::kE;
     int64_t base = 0;
     int L = 0;
     if (active) {
         base = a.ptr[seg];
         L = (int)(a.ptr[seg + 1] - base);
     }
-    Elems<E> st;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int l = lo + lane + STRIDE * e;
+        float v = 0.0f;
         if (l < L) {
             const int64_t q = base + l;
-            st.id[e] = a.idx[q];
-            st.v[e] = a.val[q];
+            st.id(e) = a.idx[q];
+            v = a.val[q];
             st.ax[e] = a.Mmap ? a.Min[a.Mmap[q]] : a.Min[q];
         } else {
-            st.id[e] = 0;
-            st.v[e] = 0.0f;
+            st.id(e) = 0;
             st.ax[e] = 0.0;
         }
         const float ri = fast_rcp((float)st.ax[e] + a.eps_log);
-        st.w[e] = st.v[e] * ri;
-        st.u[e] = st.w[e] * ri;
+        st.v(e) = v;
+        st.w(e) = v * ri;
+        st.u(e) = v * ri * ri;
     }
     if (!active) return;
     unsigned cnt[6] = {0, 0, 0, 0, 0, 0};
@@ -493,8 +515,8 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool 
 #pragma unroll
                 for (int k = 0; k < kChunk; ++k) {
                     const float tq = comp<E>(cur, e, k);
-                    LS[2 * k] = fmaf(tq, st.w[e], LS[2 * k]);
-                    LS[2 * k + 1] = fmaf(tq * tq, st.u[e], LS[2 * k + 1]);
+                    LS[2 * k] = fmaf(tq, st.w(e), LS[2 * k]);
+                    LS[2 * k + 1] = fmaf(tq, tq * st.u(e), LS[2 * k + 1]);
                 }
             }
             red.sum(LS, 0);
@@ -535,12 +557,13 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const BlockWork&
     if (active)
         for (int s = lane; s < a.r; s += G) xs[s] = a.X[(int64_t)seg * a.r + a.ids[s]];
     __syncthreads();
+    RegElems<E> st;
     if constexpr (G <= 64) {
         WaveReducer<G> red;
-        sweep_segment<G, E, true, LA>(a, seg, active, lane, 0, true, xs, red);
+        sweep_segment<G, true, LA>(a, seg, active, lane, 0, true, xs, red, st);
     } else {
         BlockReducer<G> red{red_lds, 0};
-        sweep_segment<G, E, true, LA>(a, seg, active, lane, 0, true, xs, red);
+        sweep_segment<G, true, LA>(a, seg, active, lane, 0, true, xs, red, st);
         __syncthreads();
     }
     if (active)
@@ -580,15 +603,22 @@ hipError_t launch_sweep_fused(const SweepArgs& a, const BlockWork* work, const i
 // through CoopReducer; all blocks of the launch are co-resident (cooperative launch), so
 // every wait ends.
 template <bool COOP>
-__global__ void __launch_bounds__(kLongThreads)
+__global__ void __launch_bounds__(kLongThreads, 2)
 k_sweep_long(SweepArgs a, const LongWork* __restrict__ work, double* __restrict__ partials,
              unsigned* __restrict__ flags, unsigned* __restrict__ err, int pmax) {
     __shared__ float xs[NMFKL_R_MAX];
     __shared__ float red_lds[2 * (kLongThreads / 64) * kMaxRed];
     __shared__ double tmp[(kLongThreads / kMaxRed) * kMaxRed];
     __shared__ double bcast[kMaxRed];
+    __shared__ int32_t s_id[kLongCapacity];
+    __shared__ float s_v[kLongCapacity], s_w[kLongCapacity], s_u[kLongCapacity];
     const LongWork wk = work[blockIdx.x];
     const int lane = threadIdx.x;
+    LdsElems<kLongE, kLongThreads> st;
+    st.idp = s_id + lane;
+    st.vp = s_v + lane;
+    st.wp = s_w + lane;
+    st.up = s_u + lane;
     for (int s = lane; s < a.r; s += kLongThreads) xs[s] = a.X[(int64_t)wk.seg * a.r + a.ids[s]];
     __syncthreads();
     if constexpr (COOP) {
@@ -603,11 +633,11 @@ k_sweep_long(SweepArgs a, const LongWork* __restrict__ work, double* __restrict_
         red.B = wk.B;
         red.part = wk.part;
         red.round = 0;
-        sweep_segment<kLongThreads, kLongE, false, true>(a, wk.seg, true, lane,
-                                                         wk.part * kLongCapacity, wk.part == 0, xs, red);
+        sweep_segment<kLongThreads, false, true>(a, wk.seg, true, lane, wk.part * kLongCapacity,
+                                                 wk.part == 0, xs, red, st);
     } else {
         BlockReducer<kLongThreads> red{red_lds, 0};
-        sweep_segment<kLongThreads, kLongE, false, true>(a, wk.seg, true, lane, 0, true, xs, red);
+        sweep_segment<kLongThreads, false, true>(a, wk.seg, true, lane, 0, true, xs, red, st);
     }
     __syncthreads();
     if (wk.part == 0)
