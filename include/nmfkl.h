@@ -188,6 +188,69 @@ int nmfkl_destroy(nmfkl_handle* h);
 /* Message of the last failed call on h (h may be NULL: the last failure of a create). */
 const char* nmfkl_last_error(const nmfkl_handle* h);
 
+/* ---------------------------------------------------------------- fold-in (W fixed)
+ * Fold-in solves Alg. 1's F-half for new columns of V with a trained W held fixed (the
+ * columns are independent subproblems, eq. 3): a document's x starts at the mass-matched
+ * constant sum(v) / sum(sumW) in every coordinate; pass p runs Alg. 2 once with the order
+ * of Philox stream 1, counter p (nmfkl_permutation(seed, p, 1, r)); the document stops after
+ * the first pass whose decrease of KL(v || W^T x) = sum_l (v_l log(v_l / [W^T x]_l) - v_l)
+ * + sumW . x is <= foldin_tol * KL, or after foldin_max_passes passes.  Uses alpha_F,
+ * beta_F and the inner-loop parameters of nmfkl_params.  A document's result does not
+ * depend on the other documents processed with it.  Documents of up to 2048 distinct words
+ * are supported (NMFKL_E_UNSUPPORTED beyond). */
+typedef struct nmfkl_result {
+    uint64_t req_id;
+    int32_t passes;     /* passes run */
+    double kl;          /* final KL of the document */
+    double t_submit;    /* steady-clock seconds at submit */
+    double t_done;      /* steady-clock seconds when the host observed completion */
+} nmfkl_result;
+
+typedef struct nmfkl_server nmfkl_server;
+
+/* A resident model: W (device, n x r point-major, caller-owned, unchanged while the model
+ * lives).  Validates W on the device (finite, >= 0; synchronises), computes its float64
+ * column and row sums and the pass orders. */
+int nmfkl_model_create(const float* W, int32_t n, int32_t r, const nmfkl_params* p, void* hip_stream,
+                       nmfkl_model** out);
+
+/* Fold in ndocs documents given in CSC form (device: doc_ptr[ndocs+1] int64, word_idx int32
+ * strictly increasing per document, counts float32 finite >= 0).  Outputs (device):
+ * F_out ndocs x r, passes_out, kl_out.  Validates on the device and synchronises the
+ * model's stream before returning. */
+int nmfkl_foldin(nmfkl_model* m, int32_t ndocs, const int64_t* doc_ptr, const int32_t* word_idx,
+                 const float* counts, float* F_out, int32_t* passes_out, double* kl_out);
+
+/* Counters of the fold-in kernels (params.collect_stats).  Synchronises. */
+int nmfkl_model_get_stats(nmfkl_model* m, nmfkl_stats* out);
+const char* nmfkl_model_last_error(const nmfkl_model* m);
+int nmfkl_model_destroy(nmfkl_model* m);
+
+/* Continuously batched fold-in server over a model.  `lanes` streams each run one batch of
+ * up to lane_docs documents at a time; whenever a lane is free, nmfkl_server_poll launches
+ * the oldest waiting documents on it, so documents that arrive while others are on the GPU
+ * start without waiting for them.  Admission is by memory: the words of all submitted and
+ * unfinished documents stay within mem_budget_bytes (8 bytes per word). */
+int nmfkl_server_create(nmfkl_model* m, int64_t mem_budget_bytes, int32_t lanes, int32_t lane_docs,
+                        nmfkl_server** out);
+
+/* Submit one document (host arrays, copied before returning).  NMFKL_E_NOMEM: the memory
+ * budget is full now (retry later); NMFKL_E_INVAL: malformed; NMFKL_E_UNSUPPORTED: too long. */
+int nmfkl_server_submit(nmfkl_server* s, uint64_t req_id, int32_t L, const int32_t* word_idx,
+                        const float* counts);
+
+/* Non-blocking: collect finished batches, launch waiting documents on free lanes, and return
+ * up to max_results finished documents (out[k] and f_out[k*r .. k*r+r)). */
+int nmfkl_server_poll(nmfkl_server* s, int32_t max_results, nmfkl_result* out, float* f_out,
+                      int32_t* n_out);
+
+/* Documents submitted and not yet returned by poll, and words held against the budget. */
+int nmfkl_server_pending(nmfkl_server* s, int64_t* queued, int64_t* in_flight_words);
+const char* nmfkl_server_last_error(const nmfkl_server* s);
+
+/* Waits for the lanes, then frees the server (not the model). */
+int nmfkl_server_destroy(nmfkl_server* s);
+
 #ifdef __cplusplus
 }
 #endif

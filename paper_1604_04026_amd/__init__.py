@@ -30,6 +30,9 @@ EXPORTED_SYMBOLS = [
     "nmfkl_params_default", "nmfkl_permutation", "nmfkl_create", "nmfkl_sweep_F", "nmfkl_sweep_W",
     "nmfkl_objective", "nmfkl_objective_carried", "nmfkl_invalidate_model", "nmfkl_get_stats", "nmfkl_get_timings",
     "nmfkl_reset_timings", "nmfkl_destroy", "nmfkl_last_error",
+    "nmfkl_model_create", "nmfkl_foldin", "nmfkl_model_get_stats", "nmfkl_model_last_error",
+    "nmfkl_model_destroy", "nmfkl_server_create", "nmfkl_server_submit", "nmfkl_server_poll",
+    "nmfkl_server_pending", "nmfkl_server_last_error", "nmfkl_server_destroy",
 ]
 
 
@@ -88,6 +91,11 @@ class NmfklTimings(ctypes.Structure):
                 for i, name in enumerate(TIMED)}
 
 
+class NmfklResult(ctypes.Structure):
+    _fields_ = [("req_id", ctypes.c_uint64), ("passes", ctypes.c_int32), ("kl", ctypes.c_double),
+                ("t_submit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -118,8 +126,20 @@ def load(path: str | None = None):
     lib.nmfkl_destroy.argtypes = [vp]
     lib.nmfkl_last_error.argtypes = [vp]
     lib.nmfkl_last_error.restype = ctypes.c_char_p
+    lib.nmfkl_model_create.argtypes = [vp, i32, i32, ctypes.POINTER(NmfklParams), vp, ctypes.POINTER(vp)]
+    lib.nmfkl_foldin.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+    lib.nmfkl_model_get_stats.argtypes = [vp, ctypes.POINTER(NmfklStats)]
+    lib.nmfkl_model_destroy.argtypes = [vp]
+    lib.nmfkl_server_create.argtypes = [vp, i64, i32, i32, ctypes.POINTER(vp)]
+    lib.nmfkl_server_submit.argtypes = [vp, u64, i32, vp, vp]
+    lib.nmfkl_server_poll.argtypes = [vp, i32, ctypes.POINTER(NmfklResult), vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.nmfkl_server_pending.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    lib.nmfkl_server_destroy.argtypes = [vp]
+    for name in ("nmfkl_model_last_error", "nmfkl_server_last_error"):
+        getattr(lib, name).argtypes = [vp]
+        getattr(lib, name).restype = ctypes.c_char_p
     for name in EXPORTED_SYMBOLS:
-        if name not in ("nmfkl_last_error",):
+        if not name.endswith("last_error"):
             getattr(lib, name).restype = ctypes.c_int
     if path is None:
         _lib = lib
@@ -272,3 +292,124 @@ def nmfkl_destroy(h: Handle):
         rc = load().nmfkl_destroy(h._ptr)
         h._ptr = None
         _check(rc)
+
+
+# ------------------------------------------------------------------ fold-in and serving
+def _mcheck(rc, m=None):
+    if rc != NMFKL_OK:
+        msg = load().nmfkl_model_last_error(m)
+        raise NmfklError(rc, msg.decode() if msg else "")
+
+
+class Model:
+    """An nmfkl_model over a resident W (device tensor n x r, kept alive here)."""
+
+    def __init__(self, ptr, W, r, stream):
+        self._ptr, self.W, self.r, self.stream = ptr, W, r, stream
+
+    def __del__(self):
+        try:
+            if self._ptr:
+                load().nmfkl_model_destroy(self._ptr)
+                self._ptr = None
+        except Exception:
+            pass
+
+
+def nmfkl_model_create(W, params: NmfklParams | None = None, stream=None) -> Model:
+    import torch
+    if W.dtype != torch.float32 or not W.is_cuda or not W.is_contiguous() or W.dim() != 2:
+        raise ValueError("W must be a contiguous float32 device tensor n x r")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    out = ctypes.c_void_p()
+    prm = params if params is not None else nmfkl_params_default()
+    _mcheck(load().nmfkl_model_create(W.data_ptr(), W.shape[0], W.shape[1], ctypes.byref(prm),
+                                      _stream_ptr(stream), ctypes.byref(out)))
+    return Model(out.value, W, W.shape[1], stream)
+
+
+def nmfkl_foldin(m: Model, doc_ptr, word_idx, counts):
+    """Fold in documents (device tensors, CSC form); returns device tensors (F, passes, kl)."""
+    import torch
+    nd = doc_ptr.numel() - 1
+    dev = doc_ptr.device
+    F = torch.empty((nd, m.r), dtype=torch.float32, device=dev)
+    passes = torch.empty(nd, dtype=torch.int32, device=dev)
+    kl = torch.empty(nd, dtype=torch.float64, device=dev)
+    _mcheck(load().nmfkl_foldin(m._ptr, nd, doc_ptr.data_ptr(), word_idx.data_ptr(), counts.data_ptr(),
+                                F.data_ptr(), passes.data_ptr(), kl.data_ptr()), m._ptr)
+    return F, passes, kl
+
+
+def nmfkl_model_get_stats(m: Model) -> dict:
+    s = NmfklStats()
+    _mcheck(load().nmfkl_model_get_stats(m._ptr, ctypes.byref(s)), m._ptr)
+    return s.as_dict()
+
+
+def nmfkl_model_destroy(m: Model):
+    if m._ptr:
+        rc = load().nmfkl_model_destroy(m._ptr)
+        m._ptr = None
+        _mcheck(rc)
+
+
+def _scheck(rc, s=None):
+    if rc != NMFKL_OK:
+        msg = load().nmfkl_server_last_error(s)
+        raise NmfklError(rc, msg.decode() if msg else "")
+
+
+class Server:
+    def __init__(self, ptr, model):
+        self._ptr, self.model = ptr, model
+
+    def __del__(self):
+        try:
+            if self._ptr:
+                load().nmfkl_server_destroy(self._ptr)
+                self._ptr = None
+        except Exception:
+            pass
+
+
+def nmfkl_server_create(m: Model, mem_budget_bytes: int, lanes: int = 8, lane_docs: int = 256) -> Server:
+    out = ctypes.c_void_p()
+    _scheck(load().nmfkl_server_create(m._ptr, int(mem_budget_bytes), int(lanes), int(lane_docs),
+                                       ctypes.byref(out)))
+    return Server(out.value, m)
+
+
+def nmfkl_server_submit(s: Server, req_id: int, word_idx: np.ndarray, counts: np.ndarray) -> int:
+    """Returns NMFKL_OK, or the admission code (NMFKL_E_NOMEM) when the budget is full now."""
+    idx = np.ascontiguousarray(word_idx, dtype=np.int32)
+    val = np.ascontiguousarray(counts, dtype=np.float32)
+    rc = load().nmfkl_server_submit(s._ptr, int(req_id), int(idx.size), idx.ctypes.data, val.ctypes.data)
+    if rc not in (NMFKL_OK, -2):
+        _scheck(rc, s._ptr)
+    return rc
+
+
+def nmfkl_server_poll(s: Server, max_results: int = 4096):
+    """Finished documents: list of (req_id, passes, kl, t_submit, t_done, f)."""
+    r = s.model.r
+    res = (NmfklResult * max_results)()
+    f = np.empty((max_results, r), dtype=np.float32)
+    n = ctypes.c_int32()
+    _scheck(load().nmfkl_server_poll(s._ptr, max_results, res, f.ctypes.data, ctypes.byref(n)), s._ptr)
+    return [(res[k].req_id, res[k].passes, res[k].kl, res[k].t_submit, res[k].t_done, f[k].copy())
+            for k in range(n.value)]
+
+
+def nmfkl_server_pending(s: Server):
+    q, w = ctypes.c_int64(), ctypes.c_int64()
+    _scheck(load().nmfkl_server_pending(s._ptr, ctypes.byref(q), ctypes.byref(w)), s._ptr)
+    return q.value, w.value
+
+
+def nmfkl_server_destroy(s: Server):
+    if s._ptr:
+        rc = load().nmfkl_server_destroy(s._ptr)
+        s._ptr = None
+        _scheck(rc)

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libnmfkl.so")
-SOURCES = ["nmfkl_kernels.hip", "nmfkl_capi.hip"]
+SOURCES = ["nmfkl_kernels.hip", "nmfkl_capi.hip", "nmfkl_foldin.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -1,0 +1,538 @@
+// C ABI of fold-in (W fixed) and of the continuously batched fold-in server.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "nmfkl_internal.hpp"
+
+using namespace nmfkl;
+
+namespace {
+thread_local std::string g_model_error;
+
+double now_seconds() {
+    using clk = std::chrono::steady_clock;
+    return std::chrono::duration<double>(clk::now().time_since_epoch()).count();
+}
+}  // namespace
+
+struct nmfkl_model {
+    int32_t n = 0, r = 0;
+    const float* W = nullptr;
+    nmfkl_params prm{};
+    hipStream_t stream = nullptr;
+    double* sumW = nullptr;
+    double* rowsumW = nullptr;
+    double totW = 0.0;
+    int32_t* perm = nullptr;  // [foldin_max_passes][r]
+    unsigned long long* stats = nullptr;
+    // plain fold-in scratch
+    int32_t* docs = nullptr;
+    size_t docs_cap = 0;
+    std::string err;
+};
+
+namespace {
+
+int mfail(nmfkl_model* m, int code, const std::string& msg) {
+    if (m) m->err = msg;
+    else g_model_error = msg;
+    return code;
+}
+
+#define MHIP(m, expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) return mfail(m, NMFKL_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+SweepArgs foldin_sweep_args(const nmfkl_model* m) {
+    SweepArgs a{};
+    a.r = m->r;
+    a.alpha = (float)m->prm.alpha_F;
+    a.beta = (float)m->prm.beta_F;
+    a.eps_log = (float)m->prm.eps_log;
+    a.eps_g = (float)m->prm.eps_g;
+    a.eps_x = (float)m->prm.eps_x;
+    a.t_max = m->prm.t_max;
+    a.j_max = m->prm.j_max;
+    a.literal_break = m->prm.literal_break;
+    a.guard = m->prm.guard;
+    a.sumA = m->sumW;
+    a.stats = m->prm.collect_stats ? m->stats : nullptr;
+    return a;
+}
+
+FoldinArgs foldin_args(const nmfkl_model* m, const int64_t* ptr, const int32_t* idx, const float* val,
+                       float* F, int32_t* passes, double* kl) {
+    FoldinArgs f{};
+    f.ptr = ptr;
+    f.idx = idx;
+    f.val = val;
+    f.W = m->W;
+    f.sumW = m->sumW;
+    f.rowsumW = m->rowsumW;
+    f.totW = m->totW;
+    f.perm = m->perm;
+    f.F = F;
+    f.passes = passes;
+    f.kl = kl;
+    f.r = m->r;
+    f.max_passes = m->prm.foldin_max_passes;
+    f.tol = m->prm.foldin_tol;
+    return f;
+}
+
+int variant_of_length(int64_t L) {
+    for (int v = 0; v < kFoldinVariants; ++v)
+        if (L <= kFoldinCapacity[v]) return v;
+    return -1;
+}
+
+// Documents grouped by variant; returns NMFKL_E_UNSUPPORTED for a document above the largest
+// capacity.  lists[v] holds document indices.
+int group_docs(nmfkl_model* m, const std::vector<int64_t>& len, std::vector<int32_t> lists[kFoldinVariants]) {
+    for (size_t d = 0; d < len.size(); ++d) {
+        const int v = variant_of_length(len[d]);
+        if (v < 0)
+            return mfail(m, NMFKL_E_UNSUPPORTED, "a document has " + std::to_string(len[d]) +
+                                                     " distinct words; fold-in supports up to " +
+                                                     std::to_string(kFoldinCapacity[kFoldinVariants - 1]));
+        lists[v].push_back((int32_t)d);
+    }
+    return NMFKL_OK;
+}
+
+// Launch the variants for grouped documents whose lists were uploaded to dev_docs (variant v
+// at offset off[v]).
+int launch_grouped(nmfkl_model* m, const FoldinArgs& f, const int32_t* dev_docs, const int off[kFoldinVariants],
+                   const int cnt[kFoldinVariants], hipStream_t stream) {
+    const SweepArgs a = foldin_sweep_args(m);
+    for (int v = kFoldinVariants - 1; v >= 0; --v)
+        MHIP(m, launch_foldin(f, a, v, dev_docs + off[v], cnt[v], stream));
+    return NMFKL_OK;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------- server
+struct nmfkl_server {
+    nmfkl_model* model = nullptr;
+    int64_t budget_words = 0;     // device words (index + count) that may be in flight
+    int32_t max_docs = 0;         // documents per lane batch
+    int64_t lane_words = 0;       // words per lane batch
+    struct Req {
+        uint64_t id;
+        int32_t L;
+        double t_submit;
+        std::vector<int32_t> idx;  // host copy of the document (taken at submit)
+        std::vector<float> val;
+    };
+    struct Lane {
+        hipStream_t stream = nullptr;
+        hipEvent_t done = nullptr;
+        bool busy = false;
+        int64_t* d_ptr = nullptr;
+        int32_t* d_idx = nullptr;
+        float* d_val = nullptr;
+        float* d_F = nullptr;
+        int32_t* d_passes = nullptr;
+        double* d_kl = nullptr;
+        int32_t* d_docs = nullptr;
+        int64_t* h_ptr = nullptr;   // pinned staging
+        int32_t* h_idx = nullptr;
+        float* h_val = nullptr;
+        int32_t* h_docs = nullptr;
+        float* h_F = nullptr;
+        int32_t* h_passes = nullptr;
+        double* h_kl = nullptr;
+        std::vector<Req> reqs;
+        int64_t words = 0;
+    };
+    std::vector<Lane> lanes;
+    std::deque<Req> pending;
+    int64_t words_in_flight = 0;     // pending + launched
+    struct Done {
+        uint64_t id;
+        int32_t passes;
+        double kl, t_submit, t_done;
+        std::vector<float> f;
+    };
+    std::deque<Done> done;
+    std::string err;
+};
+
+namespace {
+
+int sfail(nmfkl_server* s, int code, const std::string& msg) {
+    if (s) s->err = msg;
+    else g_model_error = msg;
+    return code;
+}
+
+#define SHIP(s, expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) return sfail(s, NMFKL_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+void release_lane(nmfkl_server::Lane& L) {
+    auto df = [](void* p) { if (p) (void)hipFree(p); };
+    auto hf = [](void* p) { if (p) (void)hipHostFree(p); };
+    df(L.d_ptr); df(L.d_idx); df(L.d_val); df(L.d_F); df(L.d_passes); df(L.d_kl); df(L.d_docs);
+    hf(L.h_ptr); hf(L.h_idx); hf(L.h_val); hf(L.h_docs); hf(L.h_F); hf(L.h_passes); hf(L.h_kl);
+    if (L.done) (void)hipEventDestroy(L.done);
+    if (L.stream) (void)hipStreamDestroy(L.stream);
+}
+
+// Collect finished lanes.
+int collect(nmfkl_server* s) {
+    const int r = s->model->r;
+    for (auto& L : s->lanes) {
+        if (!L.busy) continue;
+        const hipError_t q = hipEventQuery(L.done);
+        if (q == hipErrorNotReady) continue;
+        if (q != hipSuccess) return sfail(s, NMFKL_E_DEVICE, std::string("lane: ") + hipGetErrorString(q));
+        const double t = now_seconds();
+        for (size_t i = 0; i < L.reqs.size(); ++i) {
+            nmfkl_server::Done d;
+            d.id = L.reqs[i].id;
+            d.passes = L.h_passes[i];
+            d.kl = L.h_kl[i];
+            d.t_submit = L.reqs[i].t_submit;
+            d.t_done = t;
+            d.f.assign(L.h_F + (size_t)i * r, L.h_F + (size_t)(i + 1) * r);
+            s->done.push_back(std::move(d));
+        }
+        s->words_in_flight -= L.words;
+        L.reqs.clear();
+        L.words = 0;
+        L.busy = false;
+    }
+    return NMFKL_OK;
+}
+
+// Form a batch for every idle lane from the pending queue (FIFO) and launch it.
+int dispatch(nmfkl_server* s) {
+    nmfkl_model* m = s->model;
+    for (auto& L : s->lanes) {
+        if (L.busy || s->pending.empty()) continue;
+        int nd = 0;
+        int64_t w = 0;
+        L.h_ptr[0] = 0;
+        while (!s->pending.empty() && nd < s->max_docs && w + s->pending.front().L <= s->lane_words) {
+            nmfkl_server::Req q = std::move(s->pending.front());
+            s->pending.pop_front();
+            std::memcpy(L.h_idx + w, q.idx.data(), (size_t)q.L * sizeof(int32_t));
+            std::memcpy(L.h_val + w, q.val.data(), (size_t)q.L * sizeof(float));
+            w += q.L;
+            L.h_ptr[nd + 1] = w;
+            q.idx.clear();
+            q.val.clear();
+            L.reqs.push_back(std::move(q));
+            ++nd;
+        }
+        if (nd == 0) continue;
+        // group by variant
+        std::vector<int32_t> lists[kFoldinVariants];
+        for (int d = 0; d < nd; ++d) lists[variant_of_length(L.h_ptr[d + 1] - L.h_ptr[d])].push_back(d);
+        int off[kFoldinVariants], cnt[kFoldinVariants], pos = 0;
+        for (int v = 0; v < kFoldinVariants; ++v) {
+            off[v] = pos;
+            cnt[v] = (int)lists[v].size();
+            std::memcpy(L.h_docs + pos, lists[v].data(), lists[v].size() * sizeof(int32_t));
+            pos += cnt[v];
+        }
+        SHIP(s, hipMemcpyAsync(L.d_ptr, L.h_ptr, (size_t)(nd + 1) * sizeof(int64_t), hipMemcpyHostToDevice, L.stream));
+        SHIP(s, hipMemcpyAsync(L.d_idx, L.h_idx, (size_t)w * sizeof(int32_t), hipMemcpyHostToDevice, L.stream));
+        SHIP(s, hipMemcpyAsync(L.d_val, L.h_val, (size_t)w * sizeof(float), hipMemcpyHostToDevice, L.stream));
+        SHIP(s, hipMemcpyAsync(L.d_docs, L.h_docs, (size_t)pos * sizeof(int32_t), hipMemcpyHostToDevice, L.stream));
+        const FoldinArgs f = foldin_args(m, L.d_ptr, L.d_idx, L.d_val, L.d_F, L.d_passes, L.d_kl);
+        const int rc = launch_grouped(m, f, L.d_docs, off, cnt, L.stream);
+        if (rc) return sfail(s, rc, m->err);
+        SHIP(s, hipMemcpyAsync(L.h_F, L.d_F, (size_t)nd * m->r * sizeof(float), hipMemcpyDeviceToHost, L.stream));
+        SHIP(s, hipMemcpyAsync(L.h_passes, L.d_passes, (size_t)nd * sizeof(int32_t), hipMemcpyDeviceToHost, L.stream));
+        SHIP(s, hipMemcpyAsync(L.h_kl, L.d_kl, (size_t)nd * sizeof(double), hipMemcpyDeviceToHost, L.stream));
+        SHIP(s, hipEventRecord(L.done, L.stream));
+        L.words = w;
+        L.busy = true;
+    }
+    return NMFKL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* nmfkl_model_last_error(const nmfkl_model* m) { return m ? m->err.c_str() : g_model_error.c_str(); }
+
+int nmfkl_model_create(const float* W, int32_t n, int32_t r, const nmfkl_params* p, void* hip_stream,
+                       nmfkl_model** out) {
+    if (!out) return mfail(nullptr, NMFKL_E_INVAL, "out is null");
+    *out = nullptr;
+    if (!W) return mfail(nullptr, NMFKL_E_INVAL, "W is null");
+    if (n < 1) return mfail(nullptr, NMFKL_E_INVAL, "n must be >= 1");
+    if (r < 1 || r > NMFKL_R_MAX) return mfail(nullptr, NMFKL_E_INVAL, "r must be in [1, NMFKL_R_MAX]");
+    nmfkl_params prm;
+    if (p) prm = *p;
+    else nmfkl_params_default(&prm);
+    if (prm.foldin_max_passes < 1 || prm.foldin_max_passes > 100000 || !(prm.foldin_tol >= 0) || prm.t_max < 1 ||
+        prm.j_max < 0 || !(prm.eps_log >= 0) || !(prm.eps_g >= 0) || !(prm.eps_x >= 0) || !(prm.alpha_F >= 0) ||
+        !(prm.beta_F >= 0))
+        return mfail(nullptr, NMFKL_E_INVAL, "invalid parameters");
+    nmfkl_model* m = new (std::nothrow) nmfkl_model();
+    if (!m) return mfail(nullptr, NMFKL_E_NOMEM, "host allocation failed");
+    m->n = n;
+    m->r = r;
+    m->W = W;
+    m->prm = prm;
+    m->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    auto bail = [&](int code) {
+        g_model_error = m->err;
+        nmfkl_model_destroy(m);
+        return code;
+    };
+#define CM(expr)                                                                            \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) { mfail(m, NMFKL_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); return bail(NMFKL_E_DEVICE); } \
+    } while (0)
+    unsigned* flags = nullptr;
+    CM(hipMalloc(reinterpret_cast<void**>(&flags), sizeof(unsigned)));
+    CM(hipMemsetAsync(flags, 0, sizeof(unsigned), m->stream));
+    CM(launch_validate_factor(W, (int64_t)n * r, flags, kBadW, m->stream));
+    unsigned hf = 0;
+    CM(hipMemcpyAsync(&hf, flags, sizeof(unsigned), hipMemcpyDeviceToHost, m->stream));
+    CM(hipStreamSynchronize(m->stream));
+    (void)hipFree(flags);
+    if (hf) {
+        mfail(m, NMFKL_E_INVAL, "W negative or not finite");
+        return bail(NMFKL_E_INVAL);
+    }
+    CM(hipMalloc(reinterpret_cast<void**>(&m->sumW), sizeof(double) * NMFKL_R_MAX));
+    CM(hipMalloc(reinterpret_cast<void**>(&m->rowsumW), sizeof(double) * n));
+    const int blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, n / 64));
+    double* partials = nullptr;
+    CM(hipMalloc(reinterpret_cast<void**>(&partials), sizeof(double) * blocks * r));
+    OrderArg identity{};
+    for (int k = 0; k < r; ++k) identity.ids[k] = k;
+    CM(launch_permute_colsum(W, n, r, r, identity, nullptr, nullptr, partials, blocks, m->stream));
+    CM(launch_finalize_sums(partials, blocks, r, m->sumW, m->stream));
+    CM(launch_row_sums(W, n, r, m->rowsumW, m->stream));
+    std::vector<double> sw(r);
+    CM(hipMemcpyAsync(sw.data(), m->sumW, sizeof(double) * r, hipMemcpyDeviceToHost, m->stream));
+    const int P = prm.foldin_max_passes;
+    std::vector<int32_t> perm((size_t)P * r);
+    for (int q = 0; q < P; ++q) coordinate_order(prm.seed, (uint64_t)q, 1, r, perm.data() + (size_t)q * r);
+    CM(hipMalloc(reinterpret_cast<void**>(&m->perm), sizeof(int32_t) * perm.size()));
+    CM(hipMemcpyAsync(m->perm, perm.data(), sizeof(int32_t) * perm.size(), hipMemcpyHostToDevice, m->stream));
+    CM(hipMalloc(reinterpret_cast<void**>(&m->stats), sizeof(unsigned long long) * 6));
+    CM(hipMemsetAsync(m->stats, 0, sizeof(unsigned long long) * 6, m->stream));
+    CM(hipStreamSynchronize(m->stream));
+    (void)hipFree(partials);
+    m->totW = 0.0;
+    for (int k = 0; k < r; ++k) m->totW += sw[k];
+#undef CM
+    *out = m;
+    return NMFKL_OK;
+}
+
+int nmfkl_foldin(nmfkl_model* m, int32_t ndocs, const int64_t* doc_ptr, const int32_t* word_idx,
+                 const float* counts, float* F_out, int32_t* passes_out, double* kl_out) {
+    if (!m) return mfail(nullptr, NMFKL_E_INVAL, "null model");
+    if (ndocs < 0) return mfail(m, NMFKL_E_INVAL, "ndocs must be >= 0");
+    if (ndocs == 0) return NMFKL_OK;
+    if (!doc_ptr || !F_out || !passes_out || !kl_out) return mfail(m, NMFKL_E_INVAL, "null pointer");
+    std::vector<int64_t> ptr(ndocs + 1);
+    MHIP(m, hipMemcpyAsync(ptr.data(), doc_ptr, sizeof(int64_t) * (ndocs + 1), hipMemcpyDeviceToHost, m->stream));
+    MHIP(m, hipStreamSynchronize(m->stream));
+    if (ptr[0] != 0) return mfail(m, NMFKL_E_INVAL, "doc_ptr[0] must be 0");
+    std::vector<int64_t> len(ndocs);
+    for (int d = 0; d < ndocs; ++d) {
+        len[d] = ptr[d + 1] - ptr[d];
+        if (len[d] < 0) return mfail(m, NMFKL_E_INVAL, "doc_ptr not monotone");
+    }
+    const int64_t nnz = ptr[ndocs];
+    if (nnz > INT32_MAX) return mfail(m, NMFKL_E_UNSUPPORTED, "more than 2^31-1 words in one call");
+    if (nnz > 0 && (!word_idx || !counts)) return mfail(m, NMFKL_E_INVAL, "null word/count pointer");
+    unsigned* flags = nullptr;
+    MHIP(m, hipMalloc(reinterpret_cast<void**>(&flags), sizeof(unsigned)));
+    MHIP(m, hipMemsetAsync(flags, 0, sizeof(unsigned), m->stream));
+    MHIP(m, launch_validate_entries(doc_ptr, word_idx, counts, ndocs, m->n, nnz, flags, m->stream));
+    unsigned hf = 0;
+    MHIP(m, hipMemcpyAsync(&hf, flags, sizeof(unsigned), hipMemcpyDeviceToHost, m->stream));
+    MHIP(m, hipStreamSynchronize(m->stream));
+    (void)hipFree(flags);
+    if (hf) return mfail(m, NMFKL_E_INVAL, "invalid documents: word id out of range, ids not increasing, or count negative / not finite");
+    std::vector<int32_t> lists[kFoldinVariants];
+    int rc = group_docs(m, len, lists);
+    if (rc) return rc;
+    if ((size_t)ndocs > m->docs_cap) {
+        if (m->docs) (void)hipFree(m->docs);
+        m->docs = nullptr;
+        MHIP(m, hipMalloc(reinterpret_cast<void**>(&m->docs), sizeof(int32_t) * ndocs));
+        m->docs_cap = ndocs;
+    }
+    std::vector<int32_t> all;
+    int off[kFoldinVariants], cnt[kFoldinVariants];
+    for (int v = 0; v < kFoldinVariants; ++v) {
+        off[v] = (int)all.size();
+        cnt[v] = (int)lists[v].size();
+        all.insert(all.end(), lists[v].begin(), lists[v].end());
+    }
+    MHIP(m, hipMemcpyAsync(m->docs, all.data(), sizeof(int32_t) * all.size(), hipMemcpyHostToDevice, m->stream));
+    const FoldinArgs f = foldin_args(m, doc_ptr, word_idx, counts, F_out, passes_out, kl_out);
+    rc = launch_grouped(m, f, m->docs, off, cnt, m->stream);
+    if (rc) return rc;
+    // the list buffer is reused by the next call: keep the host copy alive until it is read
+    MHIP(m, hipStreamSynchronize(m->stream));
+    return NMFKL_OK;
+}
+
+int nmfkl_model_get_stats(nmfkl_model* m, nmfkl_stats* out) {
+    if (!m || !out) return mfail(m, NMFKL_E_INVAL, "null argument");
+    unsigned long long c[6];
+    MHIP(m, hipMemcpyAsync(c, m->stats, sizeof(c), hipMemcpyDeviceToHost, m->stream));
+    MHIP(m, hipStreamSynchronize(m->stream));
+    out->coords = (int64_t)c[0];
+    out->evals = (int64_t)c[1];
+    out->steps = (int64_t)c[2];
+    out->halvings = (int64_t)c[3];
+    out->rejects = (int64_t)c[4];
+    out->tmax_hits = (int64_t)c[5];
+    return NMFKL_OK;
+}
+
+int nmfkl_model_destroy(nmfkl_model* m) {
+    if (!m) return NMFKL_E_INVAL;
+    if (m->stream) (void)hipStreamSynchronize(m->stream);
+    auto f = [](void* p) { if (p) (void)hipFree(p); };
+    f(m->sumW); f(m->rowsumW); f(m->perm); f(m->stats); f(m->docs);
+    delete m;
+    return NMFKL_OK;
+}
+
+// ---------------------------------------------------------------------------- server
+int nmfkl_server_create(nmfkl_model* m, int64_t mem_budget_bytes, int32_t lanes, int32_t lane_docs,
+                        nmfkl_server** out) {
+    if (!out) return sfail(nullptr, NMFKL_E_INVAL, "out is null");
+    *out = nullptr;
+    if (!m) return sfail(nullptr, NMFKL_E_INVAL, "null model");
+    if (lanes < 1 || lanes > 64) return sfail(nullptr, NMFKL_E_INVAL, "lanes must be in [1, 64]");
+    if (lane_docs < 1) return sfail(nullptr, NMFKL_E_INVAL, "lane_docs must be >= 1");
+    const int64_t bytes_per_word = (int64_t)(sizeof(int32_t) + sizeof(float));
+    const int64_t max_doc_words = kFoldinCapacity[kFoldinVariants - 1];
+    if (mem_budget_bytes < max_doc_words * bytes_per_word)
+        return sfail(nullptr, NMFKL_E_INVAL, "memory budget below one largest document");
+    nmfkl_server* s = new (std::nothrow) nmfkl_server();
+    if (!s) return sfail(nullptr, NMFKL_E_NOMEM, "host allocation failed");
+    s->model = m;
+    s->budget_words = mem_budget_bytes / bytes_per_word;
+    s->max_docs = lane_docs;
+    s->lane_words = std::max<int64_t>(max_doc_words, s->budget_words / lanes);
+    s->lanes.resize(lanes);
+    const int r = m->r;
+    for (auto& L : s->lanes) {
+        auto fail_out = [&](hipError_t e) {
+            sfail(nullptr, NMFKL_E_DEVICE, std::string("server lane: ") + hipGetErrorString(e));
+            for (auto& K : s->lanes) release_lane(K);
+            delete s;
+            return NMFKL_E_DEVICE;
+        };
+        hipError_t e;
+        if ((e = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking)) != hipSuccess) return fail_out(e);
+        if ((e = hipEventCreateWithFlags(&L.done, hipEventDisableTiming)) != hipSuccess) return fail_out(e);
+        const size_t nd = (size_t)lane_docs, nw = (size_t)s->lane_words;
+        if ((e = hipMalloc(reinterpret_cast<void**>(&L.d_ptr), (nd + 1) * sizeof(int64_t))) != hipSuccess ||
+            (e = hipMalloc(reinterpret_cast<void**>(&L.d_idx), nw * sizeof(int32_t))) != hipSuccess ||
+            (e = hipMalloc(reinterpret_cast<void**>(&L.d_val), nw * sizeof(float))) != hipSuccess ||
+            (e = hipMalloc(reinterpret_cast<void**>(&L.d_F), nd * r * sizeof(float))) != hipSuccess ||
+            (e = hipMalloc(reinterpret_cast<void**>(&L.d_passes), nd * sizeof(int32_t))) != hipSuccess ||
+            (e = hipMalloc(reinterpret_cast<void**>(&L.d_kl), nd * sizeof(double))) != hipSuccess ||
+            (e = hipMalloc(reinterpret_cast<void**>(&L.d_docs), nd * sizeof(int32_t))) != hipSuccess ||
+            (e = hipHostMalloc(reinterpret_cast<void**>(&L.h_ptr), (nd + 1) * sizeof(int64_t), hipHostMallocDefault)) != hipSuccess ||
+            (e = hipHostMalloc(reinterpret_cast<void**>(&L.h_idx), nw * sizeof(int32_t), hipHostMallocDefault)) != hipSuccess ||
+            (e = hipHostMalloc(reinterpret_cast<void**>(&L.h_val), nw * sizeof(float), hipHostMallocDefault)) != hipSuccess ||
+            (e = hipHostMalloc(reinterpret_cast<void**>(&L.h_docs), nd * sizeof(int32_t), hipHostMallocDefault)) != hipSuccess ||
+            (e = hipHostMalloc(reinterpret_cast<void**>(&L.h_F), nd * r * sizeof(float), hipHostMallocDefault)) != hipSuccess ||
+            (e = hipHostMalloc(reinterpret_cast<void**>(&L.h_passes), nd * sizeof(int32_t), hipHostMallocDefault)) != hipSuccess ||
+            (e = hipHostMalloc(reinterpret_cast<void**>(&L.h_kl), nd * sizeof(double), hipHostMallocDefault)) != hipSuccess)
+            return fail_out(e);
+    }
+    *out = s;
+    return NMFKL_OK;
+}
+
+int nmfkl_server_submit(nmfkl_server* s, uint64_t req_id, int32_t L, const int32_t* word_idx, const float* counts) {
+    if (!s) return sfail(nullptr, NMFKL_E_INVAL, "null server");
+    if (L < 0 || (L > 0 && (!word_idx || !counts))) return sfail(s, NMFKL_E_INVAL, "bad document");
+    if (variant_of_length(L) < 0) return sfail(s, NMFKL_E_UNSUPPORTED, "document too long for fold-in");
+    const int32_t n = s->model->n;
+    for (int32_t l = 0; l < L; ++l) {
+        if (word_idx[l] < 0 || word_idx[l] >= n || (l > 0 && word_idx[l] <= word_idx[l - 1]))
+            return sfail(s, NMFKL_E_INVAL, "word ids must be in range and strictly increasing");
+        if (!(counts[l] >= 0.0f) || !std::isfinite(counts[l]))
+            return sfail(s, NMFKL_E_INVAL, "counts must be finite and >= 0");
+    }
+    if (s->words_in_flight + L > s->budget_words) return sfail(s, NMFKL_E_NOMEM, "memory budget exhausted");
+    nmfkl_server::Req q;
+    q.id = req_id;
+    q.L = L;
+    q.t_submit = now_seconds();
+    q.idx.assign(word_idx, word_idx + L);
+    q.val.assign(counts, counts + L);
+    s->pending.push_back(std::move(q));
+    s->words_in_flight += L;
+    return NMFKL_OK;
+}
+
+int nmfkl_server_poll(nmfkl_server* s, int32_t max_results, nmfkl_result* out, float* f_out, int32_t* n_out) {
+    if (!s || !n_out || (max_results > 0 && (!out || !f_out))) return sfail(s, NMFKL_E_INVAL, "null argument");
+    int rc = collect(s);
+    if (rc) return rc;
+    rc = dispatch(s);
+    if (rc) return rc;
+    const int r = s->model->r;
+    int k = 0;
+    while (k < max_results && !s->done.empty()) {
+        const auto& d = s->done.front();
+        out[k].req_id = d.id;
+        out[k].passes = d.passes;
+        out[k].kl = d.kl;
+        out[k].t_submit = d.t_submit;
+        out[k].t_done = d.t_done;
+        std::memcpy(f_out + (size_t)k * r, d.f.data(), (size_t)r * sizeof(float));
+        s->done.pop_front();
+        ++k;
+    }
+    *n_out = k;
+    return NMFKL_OK;
+}
+
+int nmfkl_server_pending(nmfkl_server* s, int64_t* queued, int64_t* in_flight_words) {
+    if (!s) return sfail(nullptr, NMFKL_E_INVAL, "null server");
+    int64_t busy = 0;
+    for (auto& L : s->lanes) busy += L.busy ? (int64_t)L.reqs.size() : 0;
+    if (queued) *queued = (int64_t)s->pending.size() + busy + (int64_t)s->done.size();
+    if (in_flight_words) *in_flight_words = s->words_in_flight;
+    return NMFKL_OK;
+}
+
+const char* nmfkl_server_last_error(const nmfkl_server* s) { return s ? s->err.c_str() : g_model_error.c_str(); }
+
+int nmfkl_server_destroy(nmfkl_server* s) {
+    if (!s) return NMFKL_E_INVAL;
+    for (auto& L : s->lanes) {
+        if (L.stream) (void)hipStreamSynchronize(L.stream);
+        release_lane(L);
+    }
+    delete s;
+    return NMFKL_OK;
+}
+
+}  // extern "C"

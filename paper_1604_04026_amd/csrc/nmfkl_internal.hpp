@@ -88,6 +88,28 @@ struct SweepArgs {
     int32_t t_max, j_max, literal_break, guard;
 };
 
+// Fold-in launch arguments (the method parameters travel in a SweepArgs).
+struct FoldinArgs {
+    const int64_t* ptr;      // document pointers
+    const int32_t* idx;      // word ids
+    const float* val;        // counts
+    const float* W;          // n x r, natural order
+    const double* sumW;      // r column sums of W
+    const double* rowsumW;   // n row sums of W
+    double totW;             // sum of sumW
+    const int32_t* perm;     // [max_passes][r] orders of the passes
+    float* F;                // ndocs x r results
+    int32_t* passes;         // passes run per document
+    double* kl;              // final KL per document
+    int r;
+    int max_passes;
+    double tol;
+};
+
+// Fold-in variants: 0: 16 lanes x 4, 1: 64 x 4, 2: 256 x 4, 3: 256 x 8 nonzeros.
+constexpr int kFoldinVariants = 4;
+constexpr int kFoldinCapacity[kFoldinVariants] = {64, 256, 1024, 2048};
+
 // A block of the fused binned launch: variant and its slice of the segment list.
 struct BlockWork {
     int32_t variant;   // index into the (lanes per segment, elements per lane) table
@@ -158,6 +180,10 @@ hipError_t launch_build_maps(const int64_t* csr_ptr, const int32_t* csr_idx, con
                              const int64_t* csc_ptr, const int32_t* csc_idx, const float* csc_val,
                              int64_t n, int64_t nnz, int32_t* csr2csc, int32_t* csc2csr,
                              unsigned* flags, hipStream_t stream);
+
+hipError_t launch_foldin(const FoldinArgs& f, const SweepArgs& a, int variant, const int32_t* docs,
+                         int ndocs, hipStream_t stream);
+hipError_t launch_row_sums(const float* W, int64_t n, int r, double* out, hipStream_t stream);
 
 // Validation flag bits.
 enum : unsigned {

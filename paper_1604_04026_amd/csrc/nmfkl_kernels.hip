@@ -163,8 +163,21 @@ struct LdsElems {
 // compile-time constant after unrolling at every call site.
 
 // Segments of G <= 64 lanes inside one wave: DPP / lane shuffles only.
+__device__ __forceinline__ double shfl_xor_f64(double v, int m) {
+    int2 p = *reinterpret_cast<int2*>(&v);
+    p.x = __shfl_xor(p.x, m);
+    p.y = __shfl_xor(p.y, m);
+    return *reinterpret_cast<double*>(&p);
+}
+
 template <int G>
 struct WaveReducer {
+    // float64 all-reduce over the segment's lanes (butterfly: identical on every lane)
+    __device__ __forceinline__ double sum_f64(double v) {
+#pragma unroll
+        for (int m = 1; m < G; m <<= 1) v += shfl_xor_f64(v, m);
+        return v;
+    }
     template <int NV>
     __device__ __forceinline__ void sum(float (&v)[NV], int lo) {
 #pragma unroll
@@ -182,6 +195,20 @@ template <int NT>
 struct BlockReducer {
     float* red;
     int parity;
+    double* red64;  // LDS, 2 * NT/64 doubles (float64 sums; optional)
+    __device__ __forceinline__ double sum_f64(double v) {
+        constexpr int W = NT / 64;
+#pragma unroll
+        for (int m = 1; m < 64; m <<= 1) v += shfl_xor_f64(v, m);
+        const int wv = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) red64[parity * W + wv] = v;
+        __syncthreads();
+        double t = red64[parity * W];
+#pragma unroll
+        for (int q = 1; q < W; ++q) t += red64[parity * W + q];
+        parity ^= 1;
+        return t;
+    }
     template <int NV>
     __device__ __forceinline__ void sum(float (&v)[NV], int lo) {
         constexpr int W = NT / 64;
@@ -454,15 +481,17 @@ __device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s,
 
 // The coordinates of chunk c in order (template recursion: each coordinate index is a
 // compile-time constant, so every register array is indexed statically).
+// cmap (fold-in): x and sumA are kept in the original coordinate order and step s of the
+// pass visits coordinate cmap[s]; null: they are already in the sweep's order.
 template <int CC, int E, bool LA, class Red, class St>
 __device__ __forceinline__ void chunk_steps(const SweepArgs& a, int c, const float4 (&t)[E][2],
                                             St& st, float* xs, Red& red, float (&LS)[kMaxRed],
-                                            unsigned (&cnt)[6]) {
+                                            unsigned (&cnt)[6], const int32_t* cmap = nullptr) {
     if constexpr (CC < kChunk) {
         const int s = c * kChunk + CC;
         if (s < a.r) {
-            coordinate_step<CC, E, LA>(a, s, t, st, xs, red, LS, cnt);
-            chunk_steps<CC + 1, E, LA>(a, c, t, st, xs, red, LS, cnt);
+            coordinate_step<CC, E, LA>(a, cmap ? cmap[s] : s, t, st, xs, red, LS, cnt);
+            chunk_steps<CC + 1, E, LA>(a, c, t, st, xs, red, LS, cnt, cmap);
         }
     }
 }
@@ -562,7 +591,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const BlockWork&
         WaveReducer<G> red;
         sweep_segment<G, true, LA>(a, seg, active, lane, 0, true, xs, red, st);
     } else {
-        BlockReducer<G> red{red_lds, 0};
+        BlockReducer<G> red{red_lds, 0, nullptr};
         sweep_segment<G, true, LA>(a, seg, active, lane, 0, true, xs, red, st);
         __syncthreads();
     }
@@ -636,7 +665,7 @@ k_sweep_long(SweepArgs a, const LongWork* __restrict__ work, double* __restrict_
         sweep_segment<kLongThreads, false, true>(a, wk.seg, true, lane, wk.part * kLongCapacity,
                                                  wk.part == 0, xs, red, st);
     } else {
-        BlockReducer<kLongThreads> red{red_lds, 0};
+        BlockReducer<kLongThreads> red{red_lds, 0, nullptr};
         sweep_segment<kLongThreads, false, true>(a, wk.seg, true, lane, 0, true, xs, red, st);
     }
     __syncthreads();
@@ -677,6 +706,183 @@ int long_kernel_blocks_per_cu() {
                                                      kLongThreads, 0) != hipSuccess)
         return 0;
     return nb;
+}
+
+// ------------------------------------------------------------------------ fold-in
+// Documents folded in with W fixed (Alg. 1's F-half applied to new columns): each document
+// starts from the mass-matched constant x0 = sum(v) / sum(sumW) (model x0 * rowsum(W) at
+// its nonzeros) and runs Alg. 2 passes; pass p visits the coordinates in the order
+// perm[p] (Philox stream 1) and gathers W[i][perm[p][s]] for the lane's nonzeros.  After
+// every pass the document's KL (eq. 1 restricted to the column, float64) is all-reduced;
+// the document stops after the first pass whose KL decrease is <= tol * KL, or after
+// max_passes passes.  The documents of a launch are independent: a document's result does
+// not depend on which others share the launch.
+template <int E, int STRIDE, class St>
+__device__ __forceinline__ void load_chunk_gather(const FoldinArgs& f, St& st, int L, int lane, int c,
+                                                  const int32_t* perm, float4 (&t)[E][2]) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        float q[kChunk];
+        const bool ok = lane + STRIDE * e < L;
+        const float* row = f.W + (int64_t)st.id(e) * f.r;
+#pragma unroll
+        for (int cc = 0; cc < kChunk; ++cc) {
+            const int s = c * kChunk + cc;
+            q[cc] = (ok && s < f.r) ? row[perm[s]] : 0.0f;
+        }
+        t[e][0] = make_float4(q[0], q[1], q[2], q[3]);
+        t[e][1] = make_float4(q[4], q[5], q[6], q[7]);
+    }
+}
+
+// The document's KL at the current model and x: sum_l (v log(v/ax) - v) + sum_k sumW_k x_k.
+template <int G, int E, class Red, class St>
+__device__ __forceinline__ double doc_kl(const FoldinArgs& f, St& st, int lane, const float* xs, Red& red) {
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const double v = (double)st.v(e);
+        if (v != 0.0) acc += v * log(v / st.ax[e]) - v;
+    }
+    for (int k = lane; k < f.r; k += G) acc += f.sumW[k] * (double)xs[k];
+    return red.sum_f64(acc);
+}
+
+template <int G, int E, bool LA, class Red>
+__device__ __forceinline__ void foldin_segment(const FoldinArgs& f, const SweepArgs& a, int d, bool active,
+                                               int lane, float* xs, int32_t* perm_lds, Red& red) {
+    int64_t base = 0;
+    int L = 0;
+    if (active) {
+        base = f.ptr[d];
+        L = (int)(f.ptr[d + 1] - base);
+    }
+    RegElems<E> st;
+    double mass = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int l = lane + G * e;
+        float v = 0.0f;
+        st.id(e) = 0;
+        if (l < L) {
+            st.id(e) = f.idx[base + l];
+            v = f.val[base + l];
+        }
+        st.v(e) = v;
+        mass += (double)v;
+    }
+    if (!active) return;
+    mass = red.sum_f64(mass);
+    const double x0 = mass / f.totW;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        st.ax[e] = (lane + G * e < L) ? x0 * f.rowsumW[st.id(e)] : 0.0;
+        const float ri = fast_rcp((float)st.ax[e] + a.eps_log);
+        st.w(e) = st.v(e) * ri;
+        st.u(e) = st.v(e) * ri * ri;
+    }
+    for (int k = lane; k < f.r; k += G) xs[k] = (float)x0;
+    if constexpr (G > 64) __syncthreads();
+    double kl_prev = doc_kl<G, E>(f, st, lane, xs, red);
+    double kl = kl_prev;
+    unsigned cnt[6] = {0, 0, 0, 0, 0, 0};
+    const int nchunks = (f.r + kChunk - 1) / kChunk;
+    int p = 0;
+    while (p < f.max_passes) {
+        for (int s = lane; s < f.r; s += G) perm_lds[s] = f.perm[(int64_t)p * f.r + s];
+        if constexpr (G > 64) __syncthreads();
+        for (int c = 0; c < nchunks; ++c) {
+            float4 cur[E][2];
+            load_chunk_gather<E, G>(f, st, L, lane, c, perm_lds, cur);
+            float LS[kMaxRed];
+            if constexpr (LA) {
+#pragma unroll
+                for (int i = 0; i < kMaxRed; ++i) LS[i] = 0.0f;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+#pragma unroll
+                    for (int k = 0; k < kChunk; ++k) {
+                        const float tq = comp<E>(cur, e, k);
+                        LS[2 * k] = fmaf(tq, st.w(e), LS[2 * k]);
+                        LS[2 * k + 1] = fmaf(tq, tq * st.u(e), LS[2 * k + 1]);
+                    }
+                }
+                red.sum(LS, 0);
+                cnt[1] += 1;
+            }
+            chunk_steps<0, E, LA>(a, c, cur, st, xs, red, LS, cnt, perm_lds);
+        }
+        if constexpr (G > 64) __syncthreads();
+        ++p;
+        kl = doc_kl<G, E>(f, st, lane, xs, red);
+        if (kl_prev - kl <= f.tol * kl) break;
+        kl_prev = kl;
+    }
+    for (int k = lane; k < f.r; k += G) f.F[(int64_t)d * f.r + k] = xs[k];
+    if (lane == 0) {
+        f.passes[d] = p;
+        f.kl[d] = kl;
+    }
+    if (a.stats && lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) atomicAdd(&a.stats[q], (unsigned long long)cnt[q]);
+    }
+}
+
+template <int G, int E>
+__global__ void __launch_bounds__(kFusedThreads, 2)
+k_foldin(FoldinArgs f, SweepArgs a, const int32_t* __restrict__ docs, int ndocs) {
+    constexpr int SPB = kFusedThreads / G;
+    __shared__ float xs_all[SPB * NMFKL_R_MAX];
+    __shared__ int32_t perm_all[SPB * NMFKL_R_MAX];
+    __shared__ float red[2 * (kFusedThreads / 64) * kMaxRed];
+    __shared__ double red64[2 * (kFusedThreads / 64)];
+    const int slot = threadIdx.x / G, lane = threadIdx.x % G;
+    const int di = blockIdx.x * SPB + slot;
+    const bool active = di < ndocs;
+    const int d = active ? docs[di] : 0;
+    if constexpr (G <= 64) {
+        WaveReducer<G> rd;
+        foldin_segment<G, E, true>(f, a, d, active, lane, xs_all + slot * NMFKL_R_MAX,
+                                   perm_all + slot * NMFKL_R_MAX, rd);
+    } else {
+        BlockReducer<G> rd{red, 0, red64};
+        foldin_segment<G, E, true>(f, a, d, active, lane, xs_all, perm_all, rd);
+    }
+}
+
+hipError_t launch_foldin(const FoldinArgs& f, const SweepArgs& a, int variant, const int32_t* docs,
+                         int ndocs, hipStream_t stream) {
+    if (ndocs <= 0) return hipSuccess;
+    switch (variant) {
+        case 0:
+            hipLaunchKernelGGL((k_foldin<16, 4>), dim3((ndocs + 15) / 16), dim3(kFusedThreads), 0, stream, f, a, docs, ndocs);
+            break;
+        case 1:
+            hipLaunchKernelGGL((k_foldin<64, 4>), dim3((ndocs + 3) / 4), dim3(kFusedThreads), 0, stream, f, a, docs, ndocs);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_foldin<256, 4>), dim3(ndocs), dim3(kFusedThreads), 0, stream, f, a, docs, ndocs);
+            break;
+        default:
+            hipLaunchKernelGGL((k_foldin<256, 8>), dim3(ndocs), dim3(kFusedThreads), 0, stream, f, a, docs, ndocs);
+            break;
+    }
+    return hipGetLastError();
+}
+
+// Row sums of W in float64 (one thread per row).
+__global__ void k_row_sums(const float* __restrict__ W, int64_t n, int r, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int k = 0; k < r; ++k) acc += (double)W[i * r + k];
+    out[i] = acc;
+}
+
+hipError_t launch_row_sums(const float* W, int64_t n, int r, double* out, hipStream_t stream) {
+    hipLaunchKernelGGL(k_row_sums, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, W, n, r, out);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------- model at the nonzeros + objective

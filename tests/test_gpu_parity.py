@@ -296,3 +296,34 @@ def test_carried_objective_and_refresh_mode():
     for refresh, (Dc, De, W, F) in res.items():
         assert np.all(np.abs(De - Do) / Do <= 1e-5)
         assert relf(W, Wo) <= 1e-4 and relf(F, Fo) <= 1e-4
+
+
+def test_regularised_trajectory_parity():
+    """eq. 2's L1/L2 terms (alpha_1, alpha_2, beta_1, beta_2 > 0): GPU vs oracle."""
+    prob = CASES["corpus_mid"]()
+    kw = dict(alpha_W=0.2, alpha_F=0.05, beta_W=0.01, beta_F=0.3)
+    sweeps = 6
+    dev = P.upload(prob, "cuda")
+    h = P.nmfkl_create(dev, P.nmfkl_params_default(**kw))
+    for t in range(sweeps):
+        P.nmfkl_sweep_F(h, t)
+        P.nmfkl_sweep_W(h, t)
+    Wg, Fg = dev.W.cpu().numpy(), dev.F.cpu().numpy()
+    P.nmfkl_destroy(h)
+    Wo, Fo, _ = oracle.run(prob, sweeps, oracle.params(**kw))
+    print(f"regularised: W {relf(Wg, Wo):.2e} F {relf(Fg, Fo):.2e}; zeros W {np.mean(Wg == 0):.2f} F {np.mean(Fg == 0):.2f}")
+    assert relf(Wg, Wo) <= 1e-4 and relf(Fg, Fo) <= 1e-4
+
+
+@pytest.mark.parametrize("flags", [dict(literal_break=1), dict(guard=0)])
+def test_ablation_step_parity(flags):
+    """The paper-literal inner loop (signed break test, or no descent guard): one
+    half-sweep each from an identical state, GPU vs oracle."""
+    prob = CASES["corpus_mid"]()
+    t = 2
+    ids = oracle.permutation(0, t, 0, prob.r)
+    Fo, _, _ = oracle.sweep_F(prob, prob.W0.astype(np.float64), prob.F0.astype(np.float64), ids,
+                              oracle.params(**flags))
+    Fg = gpu_half(prob, prob.W0, prob.F0, t, "F", P.nmfkl_params_default(**flags))
+    print(f"ablation {flags}: F rel {relf(Fg, Fo):.2e} flips {flips(Fg, Fo)}")
+    assert relf(Fg, Fo) <= 1e-4
