@@ -16,9 +16,18 @@ Prints one JSON line.  Besides the contract fields it carries:
   cpu_baseline  the FP64 oracle timed on the host cores on a bounded sample (the first
                 sweeps of the same workload from the same initial factors);
   kernels       every timed launch group (ms per launch, GB/s under the gather model);
-  check         the GPU objective after the first sweeps vs the oracle's on the same sweeps.
+  check         the GPU objective after the first sweeps vs the oracle's on the same sweeps;
+  batched       64 independent planted problems (n ~ U{1k..20k}, m ~ U{1k..50k}, r in
+                {10, 16, 32, 64}, density 0.1-2%), 10 sweeps: one graph launch over the batch
+                (mapping picked by the batch autotuner) against the 64 problems run one after
+                another through plain handles;
+  serving       fold-in requests (W 50,000 x 100 Gamma(0.1), Poisson arrivals at 20,000
+                documents/s, log-normal lengths up to 5,000 words) through the continuously
+                batched server, against per-request plain fold-in calls in arrival order:
+                documents/s and p50/p99 latency from arrival to the host seeing the result.
 """
 import argparse
+import collections
 import hashlib
 import json
 import os
@@ -32,8 +41,8 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1604_04026_amd", "csrc", "nmfkl_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_NAMES = {"fused_F": "k_sweep_fused", "fused_W": "k_sweep_fused", "long_F": "k_sweep_long",
-                "long_W": "k_sweep_long", "model": "k_model_objective", "sums_F": "k_permute_colsum",
-                "sums_W": "k_permute_colsum"}
+                "long_W": "k_sweep_long", "model": "k_model_terms", "sums_F": "k_permute_jobs",
+                "sums_W": "k_permute_jobs"}
 
 
 def source_hash() -> str:
@@ -77,39 +86,12 @@ def cpu_baseline(prob, seconds: float):
                       f"the same initial factors, {dt:.1f} s wall"}, D
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tuning", type=int, default=0, help="nmfkl_params.tuning bits (result-neutral)")
-    ap.add_argument("--quiet", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sweep's sharding over "
-              "several GPUs is a design, not part of this build.", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
+def sweep_leg(P, prob, args, log):
     import torch
-
-    import paper_1604_04026_amd as P
-    from paper_1604_04026_amd import workloads
-
-    log = (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
-    t0 = time.perf_counter()
-    prob = workloads.config(1, seed=args.seed)
-    log(f"[bench] workload generated: n={prob.n} m={prob.m} r={prob.r} nnz={prob.nnz} "
-        f"({time.perf_counter() - t0:.1f} s)")
-    torch.cuda.set_device(0)
     dev = P.upload(prob, "cuda:0")
     h = P.nmfkl_create(dev, P.nmfkl_params_default(seed=args.seed, collect_timings=1, tuning=args.tuning))
     torch.cuda.synchronize()
     log("[bench] handle created")
-
     D_warm = []
     for t in range(args.warmup):
         P.nmfkl_sweep_F(h, t)
@@ -117,7 +99,6 @@ def main():
         D_warm.append(P.nmfkl_objective_carried(h))
     P.nmfkl_reset_timings(h)
     log(f"[bench] warmup done, D = {D_warm}")
-
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     D = None
@@ -129,8 +110,204 @@ def main():
     elapsed = time.perf_counter() - t_start
     tim = P.nmfkl_get_timings(h)
     P.nmfkl_destroy(h)
+    del dev
     log(f"[bench] timed {args.steps} sweeps in {elapsed * 1e3:.2f} ms, final D = {D}")
+    return elapsed, tim, D_warm
 
+
+def batched_leg(P, probs, log):
+    """10 sweeps of every problem: batch graph vs 64 sequential plain handles."""
+    import numpy as np
+    import torch
+    sweeps = 10
+    nnz = sum(p.nnz for p in probs)
+    updates = 2.0 * sweeps * sum(p.nnz * p.r for p in probs)
+    # plain: each problem's sweeps through its own handle, one problem after another
+    devs = [P.upload(p, "cuda:0") for p in probs]
+    hs = [P.nmfkl_create(d, P.nmfkl_params_default()) for d in devs]
+    for h in hs:                       # warm-up sweeps (model values, caches)
+        for t in range(sweeps):
+            P.nmfkl_sweep_F(h, t)
+            P.nmfkl_sweep_W(h, t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for h in hs:
+        for t in range(sweeps, 2 * sweeps):
+            P.nmfkl_sweep_F(h, t)
+            P.nmfkl_sweep_W(h, t)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    D_plain = np.array([P.nmfkl_objective_carried(h) for h in hs])
+    for h in hs:
+        P.nmfkl_destroy(h)
+    del hs, devs
+    torch.cuda.empty_cache()
+    log(f"[bench] batched: plain sequential {t_plain * 1e3:.1f} ms")
+    # batch: autotune the mapping, warm-up run (captures the graph), timed run
+    devs = [P.upload(p, "cuda:0") for p in probs]
+    b = P.nmfkl_batch_create(devs)
+    t0 = time.perf_counter()
+    chosen = P.nmfkl_batch_tune(b, 0)
+    t_tune = time.perf_counter() - t0
+    P.nmfkl_batch_run(b, 0, sweeps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.nmfkl_batch_run(b, sweeps, sweeps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    D_batch = P.nmfkl_batch_objective(b)
+    info = P.nmfkl_batch_get_info(b)
+    P.nmfkl_batch_destroy(b)
+    del devs
+    torch.cuda.empty_cache()
+    log(f"[bench] batched: graph {t_batch * 1e3:.1f} ms (tuner {t_tune:.2f} s, {info})")
+    rel = np.abs(D_batch - D_plain) / D_plain
+    return {
+        "workload": "64 planted problems: n ~ U{1k..20k}, m ~ U{1k..50k}, r in {10,16,32,64}, "
+                    "density U[0.1%,2%], Gamma(0.1) factors, 10 sweeps",
+        "nprob": len(probs), "nnz_total": int(nnz), "sweeps": sweeps,
+        "batch_ms": round(t_batch * 1e3, 3), "plain_sequential_ms": round(t_plain * 1e3, 3),
+        "speedup": round(t_plain / t_batch, 3),
+        "batch_updates_per_s": updates / t_batch, "plain_updates_per_s": updates / t_plain,
+        "tuned": {"bin_shift": int(chosen.bin_shift), "tuning": int(chosen.tuning), "tuner_s": round(t_tune, 3)},
+        "graph_cooperative": info["graph_cooperative"],
+        "objective_rel_diff_batch_vs_plain_max": float(f"{rel.max():.2e}"),
+        "timed": "sweeps 10..19 of every problem after 10 warm-up sweeps (graph captured in the warm-up)",
+    }
+
+
+def serving_leg(P, W, arrivals, ptr, idx, val, window_s, log):
+    """Open-loop Poisson arrivals through the server, then per-request plain fold-in."""
+    import numpy as np
+    import torch
+    Wd = torch.from_numpy(W).cuda()
+    m = P.nmfkl_model_create(Wd)
+    N = len(arrivals)
+    r = W.shape[1]
+
+    def doc(d):
+        return idx[ptr[d]:ptr[d + 1]], val[ptr[d]:ptr[d + 1]]
+
+    # ---- server: continuous batching
+    srv = P.nmfkl_server_create(m, 512 << 20, lanes=8, lane_docs=256)
+    buf = P.PollBuffer(4096, r)
+    lat = np.full(N, np.nan)
+    passes = np.zeros(N, np.int32)
+    waiting = collections.deque()
+    nxt, ndone = 0, 0
+    t0 = time.monotonic() + 0.05
+    deadline = t0 + arrivals[-1] + 120.0
+    while ndone < N:
+        now = time.monotonic()
+        while nxt < N and t0 + arrivals[nxt] <= now:
+            waiting.append(nxt)
+            nxt += 1
+        while waiting:
+            d = waiting[0]
+            if P.nmfkl_server_submit(srv, d, *doc(d)) != 0:
+                break
+            waiting.popleft()
+        k = P.nmfkl_server_poll_into(srv, buf)
+        for q in range(k):
+            rec = buf.res[q]
+            lat[rec.req_id] = rec.t_done - (t0 + arrivals[rec.req_id])
+            passes[rec.req_id] = rec.passes
+        ndone += k
+        if now > deadline:
+            raise RuntimeError("serving leg did not drain")
+    t_end = time.monotonic()
+    P.nmfkl_server_destroy(srv)
+    served_s = t_end - t0
+    srv_out = {"docs": N, "wall_s": round(served_s, 3), "docs_per_s": N / served_s,
+               "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+               "p999_ms": float(np.percentile(lat, 99.9) * 1e3),
+               "passes_median": float(np.median(passes)), "passes_max": int(passes.max())}
+    log(f"[bench] serving: server {srv_out}")
+
+    # ---- plain: one nmfkl_foldin call per request, in arrival order, for window_s seconds
+    lat_p = []
+    t0 = time.monotonic() + 0.05
+    d = 0
+    while d < N:
+        now = time.monotonic()
+        if now - t0 > window_s:
+            break
+        if t0 + arrivals[d] > now:
+            continue
+        i, v = doc(d)
+        dp = torch.tensor([0, len(i)], dtype=torch.int64, device="cuda")
+        di = torch.from_numpy(i).cuda()
+        dv = torch.from_numpy(v).cuda()
+        F, ps, kl = P.nmfkl_foldin(m, dp, di, dv)
+        _ = F.cpu()
+        lat_p.append(time.monotonic() - (t0 + arrivals[d]))
+        d += 1
+    t_p = time.monotonic() - t0
+    lat_p = np.array(lat_p)
+    plain_out = {"docs_completed": int(d), "window_s": round(t_p, 3), "docs_per_s": d / t_p,
+                 "p50_ms": float(np.percentile(lat_p, 50) * 1e3), "p99_ms": float(np.percentile(lat_p, 99) * 1e3),
+                 "arrived_in_window": int(np.searchsorted(arrivals, t_p))}
+    log(f"[bench] serving: plain {plain_out}")
+    P.nmfkl_model_destroy(m)
+    return {
+        "workload": f"fold-in: W 50000x{r} Gamma(0.1) resident; {N} Poisson requests at 20000/s, "
+                    "lengths LogNormal(ln 80, 1) in [1, 5000], Zipf(1.1) words, 1+Geometric(0.6) counts; "
+                    "relative KL tolerance 1e-5",
+        "server": srv_out, "plain_per_request": plain_out,
+        "throughput_ratio": round(srv_out["docs_per_s"] / plain_out["docs_per_s"], 2),
+        "latency": "arrival time to the host observing the finished document (H2D/D2H included)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=100_000)
+    ap.add_argument("--plain-window", type=float, default=3.0, help="seconds of per-request plain fold-in")
+    ap.add_argument("--workers", type=int, default=16, help="processes generating the batched problems")
+    ap.add_argument("--tuning", type=int, default=0, help="nmfkl_params.tuning bits (result-neutral)")
+    ap.add_argument("--quiet", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sweep's sharding over "
+              "several GPUs is a design, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1604_04026_amd import workloads
+
+    log = (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
+    # every workload is generated before the process touches the GPU (the batched members in
+    # forked workers)
+    t0 = time.perf_counter()
+    prob = workloads.config(1, seed=args.seed)
+    log(f"[bench] corpus generated: n={prob.n} m={prob.m} r={prob.r} nnz={prob.nnz} "
+        f"({time.perf_counter() - t0:.1f} s)")
+    batched = None
+    if not args.no_batched:
+        t0 = time.perf_counter()
+        batched = workloads.batched_configs(seed=args.seed, workers=args.workers)
+        log(f"[bench] 64 batched problems generated, nnz {sum(p.nnz for p in batched)} "
+            f"({time.perf_counter() - t0:.1f} s)")
+    serving = None
+    if not args.no_serving:
+        t0 = time.perf_counter()
+        W = workloads.serving_model(seed=args.seed)
+        arrivals, sptr, sidx, sval = workloads.serving_requests(args.serving_requests, seed=args.seed)
+        serving = (W, arrivals, sptr, sidx, sval)
+        log(f"[bench] {args.serving_requests} serving requests generated ({time.perf_counter() - t0:.1f} s)")
+
+    import torch
+    import paper_1604_04026_amd as P
+    torch.cuda.set_device(0)
+
+    elapsed, tim, D_warm = sweep_leg(P, prob, args, log)
     updates = 2.0 * prob.nnz * prob.r * args.steps
     kernels = {}
     for name, k in tim.items():
@@ -173,6 +350,11 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
     }
+    if batched is not None:
+        out["batched"] = batched_leg(P, batched, log)
+    if serving is not None:
+        W, arrivals, sptr, sidx, sval = serving
+        out["serving"] = serving_leg(P, W, arrivals, sptr, sidx, sval, args.plain_window, log)
     if not args.no_cpu_baseline:
         base, D_orc = cpu_baseline(prob, args.cpu_seconds)
         out["cpu_baseline"] = base

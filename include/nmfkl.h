@@ -75,6 +75,11 @@ typedef struct nmfkl_params {
     int32_t collect_timings;   /* 1: bracket every launch group with HIP events (nmfkl_get_timings) */
     int32_t tuning;            /* implementation choices that do not change results; bit 0: batched
                                   (lookahead) derivative sums also for segments of 257..1024 nonzeros */
+    int32_t bin_shift;         /* mapping of segments of <= 1024 nonzeros to lanes (0..3, default 0):
+                                  a segment of L nonzeros runs on the smallest lane group that holds
+                                  L << bin_shift nonzeros (8, 16, 32, 64 or 256 lanes x 4).  Changes
+                                  the summation order of eq. 6's sums, hence results in the last
+                                  bits; results are identical for identical bin_shift */
 } nmfkl_params;
 
 typedef struct nmfkl_problem {
@@ -188,6 +193,59 @@ int nmfkl_destroy(nmfkl_handle* h);
 /* Message of the last failed call on h (h may be NULL: the last failure of a create). */
 const char* nmfkl_last_error(const nmfkl_handle* h);
 
+/* ---------------------------------------------------------------- batched problems
+ * Many independent factorisations (Alg. 1 on each; problems share nothing, as the columns
+ * and rows of one problem do in eq. 3) advanced together: every launch of a half-sweep
+ * covers all problems (the permuted copies and factor sums of every problem in one launch,
+ * the segments of every problem binned into one set of sweep launches), and the launches of
+ * a run of sweeps are captured once in a HIP graph and replayed.  A problem's results are
+ * identical to those of a handle over the same problem with the same parameters (same
+ * bin_shift) running the same sweeps. */
+typedef struct nmfkl_batch nmfkl_batch;
+
+typedef struct nmfkl_batch_info {
+    int32_t nprob;
+    int32_t bin_shift;          /* mapping in use (nmfkl_params.bin_shift) */
+    int32_t tuning;             /* nmfkl_params.tuning in use */
+    int32_t graph_cooperative;  /* 1: graphs hold cooperative launches; 0: ordinary launches of
+                                   grids within the co-resident capacity; -1: no graph yet */
+    int32_t fused_blocks[2];    /* blocks of the binned launch: F-half, W-half */
+    int32_t long_single_blocks[2];
+    int32_t long_rounds[2];     /* cooperative launches per half */
+    int64_t nnz_total;
+} nmfkl_batch_info;
+
+/* Create a batch over nprob problems (host array of nmfkl_problem whose pointers are device
+ * memory owned by the caller, valid until nmfkl_batch_destroy).  Each problem is validated
+ * as by nmfkl_create (errors name the problem).  One params for all problems.  Synchronises.
+ * Errors: NMFKL_E_INVAL, NMFKL_E_NOMEM, NMFKL_E_DEVICE, NMFKL_E_UNSUPPORTED.  On error *out
+ * is NULL and nmfkl_batch_last_error(NULL) gives the message. */
+int nmfkl_batch_create(int32_t nprob, const nmfkl_problem* probs, const nmfkl_params* p, void* hip_stream,
+                       nmfkl_batch** out);
+
+/* Outer iterations t0, ..., t0 + nsweeps - 1 of Alg. 1 (F-half then W-half) on every problem,
+ * as one graph launch on the batch's stream (the graph for this nsweeps is captured on first
+ * use and reused).  Asynchronous.  t0 >= 0, 1 <= nsweeps <= 100000. */
+int nmfkl_batch_run(nmfkl_batch* b, int32_t t0, int32_t nsweeps);
+
+/* eq. 1 of every problem (nprob doubles, host), from the carried model values as
+ * nmfkl_objective_carried.  Synchronises; reports a failed cross-block wait as
+ * NMFKL_E_DEVICE. */
+int nmfkl_batch_objective(nmfkl_batch* b, double* D_out);
+
+/* Autotuner: times one outer iteration (iteration t) under each candidate mapping
+ * (bin_shift 0..2, tuning bit 0 off/on) on the batch, restoring W, F and the model values after
+ * every trial, and keeps the fastest.  The factors are unchanged on return.  chosen (host,
+ * may be NULL) receives the parameters now in use, with which nmfkl_create reproduces the
+ * batch's results.  Synchronises. */
+int nmfkl_batch_tune(nmfkl_batch* b, int32_t t, nmfkl_params* chosen);
+
+int nmfkl_batch_get_info(nmfkl_batch* b, nmfkl_batch_info* out);
+const char* nmfkl_batch_last_error(const nmfkl_batch* b);
+
+/* Synchronises the stream, then frees the batch's scratch (not the problems' memory). */
+int nmfkl_batch_destroy(nmfkl_batch* b);
+
 /* ---------------------------------------------------------------- fold-in (W fixed)
  * Fold-in solves Alg. 1's F-half for new columns of V with a trained W held fixed (the
  * columns are independent subproblems, eq. 3): a document's x starts at the mass-matched
@@ -196,7 +254,7 @@ const char* nmfkl_last_error(const nmfkl_handle* h);
  * the first pass whose decrease of KL(v || W^T x) = sum_l (v_l log(v_l / [W^T x]_l) - v_l)
  * + sumW . x is <= foldin_tol * KL, or after foldin_max_passes passes.  Uses alpha_F,
  * beta_F and the inner-loop parameters of nmfkl_params.  A document's result does not
- * depend on the other documents processed with it.  Documents of up to 2048 distinct words
+ * depend on the other documents processed with it.  Documents of up to 5120 distinct words
  * are supported (NMFKL_E_UNSUPPORTED beyond). */
 typedef struct nmfkl_result {
     uint64_t req_id;

@@ -33,6 +33,8 @@ EXPORTED_SYMBOLS = [
     "nmfkl_model_create", "nmfkl_foldin", "nmfkl_model_get_stats", "nmfkl_model_last_error",
     "nmfkl_model_destroy", "nmfkl_server_create", "nmfkl_server_submit", "nmfkl_server_poll",
     "nmfkl_server_pending", "nmfkl_server_last_error", "nmfkl_server_destroy",
+    "nmfkl_batch_create", "nmfkl_batch_run", "nmfkl_batch_objective", "nmfkl_batch_tune",
+    "nmfkl_batch_get_info", "nmfkl_batch_last_error", "nmfkl_batch_destroy",
 ]
 
 
@@ -54,6 +56,7 @@ class NmfklParams(ctypes.Structure):
         ("foldin_max_passes", ctypes.c_int32), ("foldin_tol", ctypes.c_double),
         ("refresh_model", ctypes.c_int32), ("collect_stats", ctypes.c_int32),
         ("collect_timings", ctypes.c_int32), ("tuning", ctypes.c_int32),
+        ("bin_shift", ctypes.c_int32),
     ]
 
 
@@ -89,6 +92,20 @@ class NmfklTimings(ctypes.Structure):
     def as_dict(self):
         return {name: {f: getattr(self.k[i], f) for f, _ in NmfklKernelTiming._fields_}
                 for i, name in enumerate(TIMED)}
+
+
+class NmfklBatchInfo(ctypes.Structure):
+    _fields_ = [("nprob", ctypes.c_int32), ("bin_shift", ctypes.c_int32), ("tuning", ctypes.c_int32),
+                ("graph_cooperative", ctypes.c_int32), ("fused_blocks", ctypes.c_int32 * 2),
+                ("long_single_blocks", ctypes.c_int32 * 2), ("long_rounds", ctypes.c_int32 * 2),
+                ("nnz_total", ctypes.c_int64)]
+
+    def as_dict(self):
+        out = {}
+        for f, _ in self._fields_:
+            v = getattr(self, f)
+            out[f] = list(v) if isinstance(v, ctypes.Array) else int(v)
+        return out
 
 
 class NmfklResult(ctypes.Structure):
@@ -135,7 +152,14 @@ def load(path: str | None = None):
     lib.nmfkl_server_poll.argtypes = [vp, i32, ctypes.POINTER(NmfklResult), vp, ctypes.POINTER(ctypes.c_int32)]
     lib.nmfkl_server_pending.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     lib.nmfkl_server_destroy.argtypes = [vp]
-    for name in ("nmfkl_model_last_error", "nmfkl_server_last_error"):
+    lib.nmfkl_batch_create.argtypes = [i32, ctypes.POINTER(NmfklProblem), ctypes.POINTER(NmfklParams), vp,
+                                       ctypes.POINTER(vp)]
+    lib.nmfkl_batch_run.argtypes = [vp, i32, i32]
+    lib.nmfkl_batch_objective.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    lib.nmfkl_batch_tune.argtypes = [vp, i32, ctypes.POINTER(NmfklParams)]
+    lib.nmfkl_batch_get_info.argtypes = [vp, ctypes.POINTER(NmfklBatchInfo)]
+    lib.nmfkl_batch_destroy.argtypes = [vp]
+    for name in ("nmfkl_model_last_error", "nmfkl_server_last_error", "nmfkl_batch_last_error"):
         getattr(lib, name).argtypes = [vp]
         getattr(lib, name).restype = ctypes.c_char_p
     for name in EXPORTED_SYMBOLS:
@@ -402,6 +426,23 @@ def nmfkl_server_poll(s: Server, max_results: int = 4096):
             for k in range(n.value)]
 
 
+class PollBuffer:
+    """Reusable result buffers for nmfkl_server_poll_into (no allocation per poll)."""
+
+    def __init__(self, max_results: int, r: int):
+        self.max_results = max_results
+        self.res = (NmfklResult * max_results)()
+        self.f = np.empty((max_results, r), dtype=np.float32)
+        self.n = ctypes.c_int32()
+
+
+def nmfkl_server_poll_into(s: Server, buf: PollBuffer) -> int:
+    """Like nmfkl_server_poll into buf.res / buf.f; returns the number of results."""
+    _scheck(load().nmfkl_server_poll(s._ptr, buf.max_results, buf.res, buf.f.ctypes.data,
+                                     ctypes.byref(buf.n)), s._ptr)
+    return buf.n.value
+
+
 def nmfkl_server_pending(s: Server):
     q, w = ctypes.c_int64(), ctypes.c_int64()
     _scheck(load().nmfkl_server_pending(s._ptr, ctypes.byref(q), ctypes.byref(w)), s._ptr)
@@ -413,3 +454,65 @@ def nmfkl_server_destroy(s: Server):
         rc = load().nmfkl_server_destroy(s._ptr)
         s._ptr = None
         _scheck(rc)
+
+
+# ------------------------------------------------------------------ batched problems
+def _bcheck(rc, b=None):
+    if rc != NMFKL_OK:
+        msg = load().nmfkl_batch_last_error(b)
+        raise NmfklError(rc, msg.decode() if msg else "")
+
+
+class Batch:
+    """An nmfkl_batch over device problems (kept alive here)."""
+
+    def __init__(self, ptr, devs, stream):
+        self._ptr, self.devs, self.stream = ptr, devs, stream
+
+    def __del__(self):
+        try:
+            if self._ptr:
+                load().nmfkl_batch_destroy(self._ptr)
+                self._ptr = None
+        except Exception:
+            pass
+
+
+def nmfkl_batch_create(devs, params: NmfklParams | None = None, stream=None) -> Batch:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    arr = (NmfklProblem * len(devs))(*[d.struct() for d in devs])
+    out = ctypes.c_void_p()
+    prm = params if params is not None else nmfkl_params_default()
+    _bcheck(load().nmfkl_batch_create(len(devs), arr, ctypes.byref(prm), _stream_ptr(stream), ctypes.byref(out)))
+    return Batch(out.value, list(devs), stream)
+
+
+def nmfkl_batch_run(b: Batch, t0: int, nsweeps: int):
+    _bcheck(load().nmfkl_batch_run(b._ptr, int(t0), int(nsweeps)), b._ptr)
+
+
+def nmfkl_batch_objective(b: Batch) -> np.ndarray:
+    D = np.empty(len(b.devs), dtype=np.float64)
+    _bcheck(load().nmfkl_batch_objective(b._ptr, D.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), b._ptr)
+    return D
+
+
+def nmfkl_batch_tune(b: Batch, t: int = 0) -> NmfklParams:
+    out = NmfklParams()
+    _bcheck(load().nmfkl_batch_tune(b._ptr, int(t), ctypes.byref(out)), b._ptr)
+    return out
+
+
+def nmfkl_batch_get_info(b: Batch) -> dict:
+    info = NmfklBatchInfo()
+    _bcheck(load().nmfkl_batch_get_info(b._ptr, ctypes.byref(info)), b._ptr)
+    return info.as_dict()
+
+
+def nmfkl_batch_destroy(b: Batch):
+    if b._ptr:
+        rc = load().nmfkl_batch_destroy(b._ptr)
+        b._ptr = None
+        _bcheck(rc)

@@ -6,7 +6,6 @@
 #include <cstring>
 #include <new>
 #include <string>
-#include <string>
 #include <vector>
 
 #include "nmfkl_internal.hpp"
@@ -34,6 +33,18 @@ struct BinPlan {
     // algorithmic (gather-model) bytes and updates of the fused and of the long launches
     double fused_bytes = 0, fused_updates = 0, long_bytes = 0, long_updates = 0;
 };
+
+// The segments of one problem's half, for planning: host copy of the segment pointers.
+struct SegSource {
+    const std::vector<int64_t>* ptr;
+    int r;
+    int prob;   // entry of the argument table
+};
+
+// Entries of a handle's device argument table (by the storage order of the model values
+// the half reads) and of its permute-job table.
+enum { kArgFfromCsr = 0, kArgFfromCsc = 1, kArgWfromCsc = 2, kArgWfromCsr = 3, kNumArgs = 4 };
+enum { kJobF = 0, kJobW = 1, kJobSumW = 2, kJobSumF = 3, kNumJobs = 4 };
 
 }  // namespace
 
@@ -64,6 +75,9 @@ struct nmfkl_handle {
     unsigned* dev_err = nullptr;       // device-side error flags (bounded waits)
     int long_capacity = 0;             // co-resident long-segment blocks
     BinPlan binF, binW;
+    std::vector<int64_t> hptr_csc, hptr_csr;  // host copies of the segment pointers
+    SweepArgs* argtab = nullptr;       // device: kNumArgs sweep-argument entries
+    PermJob* jobtab = nullptr;         // device: kNumJobs permute jobs
     // timing (params.collect_timings): event pairs per launch group, resolved on demand
     struct Pending { int kind; hipEvent_t a, b; };
     std::vector<Pending> pending;
@@ -150,79 +164,117 @@ void release(nmfkl_handle* h) {
     f(h->csc2csr); f(h->csr2csc); f(h->obj_partials); f(h->sums2); f(h->dscal); f(h->stats);
     f(h->binF.work); f(h->binF.segs); f(h->binW.work); f(h->binW.segs);
     f(h->binF.long_work); f(h->binW.long_work);
-    f(h->coop_partials); f(h->coop_counters); f(h->dev_err);
+    f(h->coop_partials); f(h->coop_counters); f(h->dev_err); f(h->argtab); f(h->jobtab);
     if (h->host_scal) (void)hipHostFree(h->host_scal);
 }
 
-// Variant for a segment of length L in the fused launch (-1: too long).
-int variant_for(int64_t L) {
+// Variant for a segment of length L in the fused launch (-1: too long).  bin_shift > 0 maps
+// a segment to the smallest variant holding L << bin_shift nonzeros (more lanes per nonzero;
+// the largest variant at most).
+int variant_for(int64_t L, int bin_shift) {
+    if (L > kMaxFusedLength) return -1;
+    const int64_t Ls = L << bin_shift;
     for (int v = 0; v < kNumVariants; ++v)
-        if (L <= (int64_t)kVariants[v].G * kVariants[v].E) return v;
-    return -1;
+        if (Ls <= (int64_t)kVariants[v].G * kVariants[v].E) return v;
+    return kNumVariants - 1;
+}
+
+void free_plan(BinPlan* p) {
+    auto f = [](void* q) { if (q) (void)hipFree(q); };
+    f(p->work); f(p->segs); f(p->long_work);
+    *p = BinPlan{};
 }
 
 // Segments up to kMaxFusedLength: grouped by variant (longest variants first, so that long
-// blocks start early) and cut into blocks of kFusedThreads / G segments.  Longer segments:
-// B = ceil(L / kLongCapacity) blocks each, packed longest first into cooperative rounds of at
-// most long_capacity blocks.
-int plan_bins(nmfkl_handle* h, const int64_t* dptr, int64_t Q, BinPlan* plan) {
-    std::vector<int64_t> ptr(Q + 1);
-    HIP_TRY(h, hipMemcpy(ptr.data(), dptr, (Q + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
-    auto len = [&](int32_t q) { return ptr[q + 1] - ptr[q]; };
-    std::vector<std::vector<int32_t>> groups(kNumVariants);
-    std::vector<int32_t> longs;
-    for (int64_t q = 0; q < Q; ++q) {
-        const int v = variant_for(len((int32_t)q));
-        if (v < 0) longs.push_back((int32_t)q);
-        else groups[v].push_back((int32_t)q);
+// blocks start early); inside a variant each problem's segments are sorted longest first and
+// cut into blocks of kFusedThreads / G segments of that problem, and the blocks of all
+// problems are ordered by their first segment, longest first.  Longer segments: B =
+// ceil(L / kLongCapacity) blocks each; those with B = 1 in one ordinary launch, the others
+// packed longest first into cooperative rounds of at most long_capacity blocks.
+int plan_bins(const std::vector<SegSource>& src, int long_capacity, int bin_shift, BinPlan* plan,
+              std::string* err) {
+    struct LongSeg { int32_t q, prob; int64_t len; };
+    const size_t ns = src.size();
+    std::vector<std::vector<std::vector<int32_t>>> groups(kNumVariants, std::vector<std::vector<int32_t>>(ns));
+    std::vector<LongSeg> longs;
+    for (size_t i = 0; i < ns; ++i) {
+        const std::vector<int64_t>& ptr = *src[i].ptr;
+        const double r = src[i].r;
+        const int64_t Q = (int64_t)ptr.size() - 1;
+        for (int64_t q = 0; q < Q; ++q) {
+            const int64_t L = ptr[q + 1] - ptr[q];
+            const double bytes = (double)L * (8.0 + 4.0 * r) + 8.0 + 8.0 * r;
+            const int v = variant_for(L, bin_shift);
+            if (v < 0) {
+                longs.push_back(LongSeg{(int32_t)q, src[i].prob, L});
+                plan->long_bytes += bytes;
+                plan->long_updates += (double)L * r;
+            } else {
+                groups[v][i].push_back((int32_t)q);
+                plan->fused_bytes += bytes;
+                plan->fused_updates += (double)L * r;
+            }
+        }
     }
-    const double r = h->prob.r;
-    auto seg_bytes = [&](int32_t q) { return (double)len(q) * (8.0 + 4.0 * r) + 8.0 + 8.0 * r; };
-    for (int v = 0; v < kNumVariants; ++v)
-        for (int32_t q : groups[v]) { plan->fused_bytes += seg_bytes(q); plan->fused_updates += (double)len(q) * r; }
-    for (int32_t q : longs) { plan->long_bytes += seg_bytes(q); plan->long_updates += (double)len(q) * r; }
     std::vector<int32_t> segs;
     std::vector<BlockWork> work;
     for (int v = kNumVariants - 1; v >= 0; --v) {
         const int spb = kFusedThreads / kVariants[v].G;
-        auto& g = groups[v];
-        std::stable_sort(g.begin(), g.end(), [&](int32_t a, int32_t b) { return len(a) > len(b); });
-        for (size_t i = 0; i < g.size(); i += spb) {
+        struct Blk { int64_t key; size_t src, first; int count; };
+        std::vector<Blk> blks;
+        for (size_t i = 0; i < ns; ++i) {
+            const std::vector<int64_t>& ptr = *src[i].ptr;
+            auto len = [&](int32_t q) { return ptr[q + 1] - ptr[q]; };
+            auto& g = groups[v][i];
+            std::stable_sort(g.begin(), g.end(), [&](int32_t a, int32_t b) { return len(a) > len(b); });
+            for (size_t k = 0; k < g.size(); k += spb)
+                blks.push_back(Blk{len(g[k]), i, k, (int)std::min<size_t>(spb, g.size() - k)});
+        }
+        std::stable_sort(blks.begin(), blks.end(), [](const Blk& a, const Blk& b) { return a.key > b.key; });
+        for (const Blk& b : blks) {
             BlockWork w;
             w.variant = v;
             w.first = (int32_t)segs.size();
-            w.count = (int32_t)std::min<size_t>(spb, g.size() - i);
-            w.pad = 0;
-            for (int k = 0; k < w.count; ++k) segs.push_back(g[i + k]);
+            w.count = b.count;
+            w.prob = src[b.src].prob;
+            for (int k = 0; k < b.count; ++k) segs.push_back(groups[v][b.src][b.first + k]);
             work.push_back(w);
         }
     }
+    auto dev_fail = [&](hipError_t e, const char* what) {
+        *err = std::string(what) + ": " + hipGetErrorString(e);
+        return NMFKL_E_DEVICE;
+    };
+    hipError_t e;
     plan->nblocks = (int)work.size();
-    HIP_TRY(h, dalloc(&plan->work, work.size()));
-    HIP_TRY(h, dalloc(&plan->segs, segs.size()));
-    if (!work.empty())
-        HIP_TRY(h, hipMemcpy(plan->work, work.data(), work.size() * sizeof(BlockWork), hipMemcpyHostToDevice));
-    if (!segs.empty())
-        HIP_TRY(h, hipMemcpy(plan->segs, segs.data(), segs.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    if ((e = dalloc(&plan->work, work.size())) != hipSuccess) return dev_fail(e, "plan allocation");
+    if ((e = dalloc(&plan->segs, segs.size())) != hipSuccess) return dev_fail(e, "plan allocation");
+    if (!work.empty() &&
+        (e = hipMemcpy(plan->work, work.data(), work.size() * sizeof(BlockWork), hipMemcpyHostToDevice)) != hipSuccess)
+        return dev_fail(e, "plan upload");
+    if (!segs.empty() &&
+        (e = hipMemcpy(plan->segs, segs.data(), segs.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess)
+        return dev_fail(e, "plan upload");
 
-    std::stable_sort(longs.begin(), longs.end(), [&](int32_t a, int32_t b) { return len(a) > len(b); });
+    std::stable_sort(longs.begin(), longs.end(), [](const LongSeg& a, const LongSeg& b) { return a.len > b.len; });
     std::vector<LongWork> lw;
-    for (int32_t q : longs)
-        if (len(q) <= kLongCapacity) lw.push_back(LongWork{q, 0, 1, 0});
+    for (const LongSeg& l : longs)
+        if (l.len <= kLongCapacity) lw.push_back(LongWork{l.q, 0, 1, 0, l.prob, 0});
     plan->single_blocks = (int)lw.size();
     BinPlan::Round cur{(int)lw.size(), 0, 0, 0};
-    for (int32_t q : longs) {
-        const int B = (int)((len(q) + kLongCapacity - 1) / kLongCapacity);
+    for (const LongSeg& l : longs) {
+        const int B = (int)((l.len + kLongCapacity - 1) / kLongCapacity);
         if (B == 1) continue;
-        if (B > h->long_capacity)
-            return fail(h, NMFKL_E_UNSUPPORTED,
-                        "a segment of " + std::to_string(len(q)) + " nonzeros needs " + std::to_string(B) +
-                            " co-resident blocks; this device holds " + std::to_string(h->long_capacity));
-        if (cur.nblocks + B > h->long_capacity) {
+        if (B > long_capacity) {
+            *err = "a segment of " + std::to_string(l.len) + " nonzeros needs " + std::to_string(B) +
+                   " co-resident blocks; this device holds " + std::to_string(long_capacity);
+            return NMFKL_E_UNSUPPORTED;
+        }
+        if (cur.nblocks + B > long_capacity) {
             plan->rounds.push_back(cur);
             cur = BinPlan::Round{(int)lw.size(), 0, 0, 0};
         }
-        for (int p = 0; p < B; ++p) lw.push_back(LongWork{q, p, B, cur.ngroups});
+        for (int p = 0; p < B; ++p) lw.push_back(LongWork{l.q, p, B, cur.ngroups, l.prob, 0});
         cur.nblocks += B;
         cur.ngroups += 1;
         cur.pmax = std::max(cur.pmax, B);
@@ -233,8 +285,10 @@ int plan_bins(nmfkl_handle* h, const int64_t* dptr, int64_t Q, BinPlan* plan) {
         plan->max_pmax = std::max(plan->max_pmax, r.pmax);
     }
     if (!lw.empty()) {
-        HIP_TRY(h, dalloc(&plan->long_work, lw.size()));
-        HIP_TRY(h, hipMemcpy(plan->long_work, lw.data(), lw.size() * sizeof(LongWork), hipMemcpyHostToDevice));
+        if ((e = dalloc(&plan->long_work, lw.size())) != hipSuccess) return dev_fail(e, "plan allocation");
+        if ((e = hipMemcpy(plan->long_work, lw.data(), lw.size() * sizeof(LongWork), hipMemcpyHostToDevice)) !=
+            hipSuccess)
+            return dev_fail(e, "plan upload");
     }
     return NMFKL_OK;
 }
@@ -251,6 +305,7 @@ int check_params(const nmfkl_params* p, std::string* why) {
     if (p->j_max < 0 || p->j_max > 64) return bad("j_max must be in [0, 64]");
     if (p->foldin_max_passes < 1) return bad("foldin_max_passes must be >= 1");
     if (!(p->foldin_tol >= 0)) return bad("foldin_tol must be >= 0");
+    if (p->bin_shift < 0 || p->bin_shift > 3) return bad("bin_shift must be in [0, 3]");
     return NMFKL_OK;
 }
 
@@ -279,6 +334,53 @@ SweepArgs sweep_args(nmfkl_handle* h, bool fhalf) {
     return a;
 }
 
+// The handle's argument entries: each half reading the model values in either storage order
+// (through the position map when they are in the other half's order).
+void make_args(nmfkl_handle* h, SweepArgs (&args)[kNumArgs]) {
+    for (int k = 0; k < kNumArgs; ++k) {
+        const bool fhalf = k == kArgFfromCsr || k == kArgFfromCsc;
+        args[k] = sweep_args(h, fhalf);
+    }
+    args[kArgFfromCsr].Min = h->Mcsr; args[kArgFfromCsr].Mmap = h->csc2csr; args[kArgFfromCsr].Mout = h->Mcsc;
+    // in-place read/write of Mcsc is safe: each entry is read and written by one lane
+    args[kArgFfromCsc].Min = h->Mcsc; args[kArgFfromCsc].Mmap = nullptr; args[kArgFfromCsc].Mout = h->Mcsc;
+    args[kArgWfromCsc].Min = h->Mcsc; args[kArgWfromCsc].Mmap = h->csr2csc; args[kArgWfromCsc].Mout = h->Mcsr;
+    args[kArgWfromCsr].Min = h->Mcsr; args[kArgWfromCsr].Mmap = nullptr; args[kArgWfromCsr].Mout = h->Mcsr;
+}
+
+// Permute jobs of the handle: the two halves' fixed factors in the order of (seed, t), and W
+// and F in their natural order for the objective.
+void make_jobs(nmfkl_handle* h, PermJob (&jobs)[kNumJobs]) {
+    const nmfkl_problem& pr = h->prob;
+    for (int k = 0; k < kNumJobs; ++k) {
+        PermJob j{};
+        const bool onW = k == kJobF || k == kJobSumW;
+        j.A = onW ? pr.W : pr.F;
+        j.P = onW ? pr.n : pr.m;
+        j.rpb = (j.P + h->sum_blocks - 1) / h->sum_blocks;
+        j.partials = h->partials;
+        j.seed = h->prm.seed;
+        j.stream = 0;
+        j.r = pr.r;
+        j.Sp = h->Sp;
+        j.first_block = 0;
+        j.nblocks = h->sum_blocks;
+        j.first_sum = 0;
+        if (k == kJobF || k == kJobW) {
+            j.Ap = h->Ap;
+            j.sums = h->sumA;
+            j.ids = h->ids;
+            j.identity = 0;
+        } else {
+            j.Ap = nullptr;
+            j.sums = h->sums2 + (k == kJobSumW ? 0 : pr.r);
+            j.ids = nullptr;
+            j.identity = 1;
+        }
+        jobs[k] = j;
+    }
+}
+
 // Model values at the nonzeros in CSC order from scratch (the objective's SDDMM pass).
 int refresh_model(nmfkl_handle* h) {
     const nmfkl_problem& pr = h->prob;
@@ -288,6 +390,26 @@ int refresh_model(nmfkl_handle* h) {
     timer_end(h, tm);
     h->model = kModelCscFresh;
     return NMFKL_OK;
+}
+
+// Enqueues one half-sweep's sweep launches (long single-block, cooperative rounds, fused)
+// over the plan, with the argument table tab; timed: bracket them with the handle's timers.
+hipError_t enqueue_plan(const BinPlan& plan, const SweepArgs* tab, double* coop_partials, unsigned* coop_flags,
+                        unsigned* dev_err, bool cooperative, bool lookahead, hipStream_t s,
+                        nmfkl_handle* timed, int long_kind, int fused_kind) {
+    hipError_t e;
+    const bool any_long = plan.single_blocks > 0 || !plan.rounds.empty();
+    const int tl = (timed && any_long) ? timer_begin(timed, long_kind) : -1;
+    if ((e = launch_sweep_long_single(tab, plan.long_work, plan.single_blocks, s)) != hipSuccess) return e;
+    for (const auto& rd : plan.rounds)
+        if ((e = launch_sweep_long(tab, plan.long_work + rd.first, rd.nblocks, coop_partials, coop_flags,
+                                   rd.ngroups, dev_err, rd.pmax, cooperative, s)) != hipSuccess)
+            return e;
+    if (timed) timer_end(timed, tl);
+    const int tf = (timed && plan.nblocks) ? timer_begin(timed, fused_kind) : -1;
+    if ((e = launch_sweep_fused(tab, plan.work, plan.segs, plan.nblocks, lookahead, s)) != hipSuccess) return e;
+    if (timed) timer_end(timed, tf);
+    return hipSuccess;
 }
 
 int half_sweep(nmfkl_handle* h, int32_t t, bool fhalf) {
@@ -305,37 +427,17 @@ int half_sweep(nmfkl_handle* h, int32_t t, bool fhalf) {
         const int rc = refresh_model(h);
         if (rc) return rc;
     }
-    const float* A = fhalf ? pr.W : pr.F;
-    const int64_t P = fhalf ? pr.n : pr.m;
     const int ts = timer_begin(h, fhalf ? NMFKL_T_SUMS_F : NMFKL_T_SUMS_W);
-    OrderArg order{};
-    coordinate_order(h->prm.seed, (uint64_t)t, 0, pr.r, order.ids);
-    HIP_TRY(h, launch_permute_colsum(A, P, pr.r, h->Sp, order, h->ids, h->Ap, h->partials, h->sum_blocks, h->stream));
-    HIP_TRY(h, launch_finalize_sums(h->partials, h->sum_blocks, pr.r, h->sumA, h->stream));
+    const PermJob* job = h->jobtab + (fhalf ? kJobF : kJobW);
+    HIP_TRY(h, launch_permute_jobs(job, 1, h->sum_blocks, t, nullptr, h->stream));
+    HIP_TRY(h, launch_finalize_jobs(job, 1, pr.r, h->stream));
     timer_end(h, ts);
-    SweepArgs a = sweep_args(h, fhalf);
-    if (fhalf) {
-        const bool from_csc = h->model == kModelCsc || h->model == kModelCscFresh;
-        a.Min = from_csc ? h->Mcsc : h->Mcsr;
-        a.Mmap = from_csc ? nullptr : h->csc2csr;
-        a.Mout = h->Mcsc;
-        // in-place read/write of Mcsc is safe: each entry is read and written by one lane
-    } else {
-        const bool from_csr = h->model == kModelCsr;
-        a.Min = from_csr ? h->Mcsr : h->Mcsc;
-        a.Mmap = from_csr ? nullptr : h->csr2csc;
-        a.Mout = h->Mcsr;
-    }
-    const bool any_long = plan.single_blocks > 0 || !plan.rounds.empty();
-    const int tl = any_long ? timer_begin(h, fhalf ? NMFKL_T_LONG_F : NMFKL_T_LONG_W) : -1;
-    HIP_TRY(h, launch_sweep_long_single(a, plan.long_work, plan.single_blocks, h->stream));
-    for (const auto& rd : plan.rounds)
-        HIP_TRY(h, launch_sweep_long(a, plan.long_work + rd.first, rd.nblocks, h->coop_partials,
-                                     h->coop_counters, rd.ngroups, h->dev_err, rd.pmax, h->stream));
-    timer_end(h, tl);
-    const int tf = plan.nblocks ? timer_begin(h, fhalf ? NMFKL_T_FUSED_F : NMFKL_T_FUSED_W) : -1;
-    HIP_TRY(h, launch_sweep_fused(a, plan.work, plan.segs, plan.nblocks, (h->prm.tuning & 1) != 0, h->stream));
-    timer_end(h, tf);
+    int ai;
+    if (fhalf) ai = (h->model == kModelCsc || h->model == kModelCscFresh) ? kArgFfromCsc : kArgFfromCsr;
+    else ai = h->model == kModelCsr ? kArgWfromCsr : kArgWfromCsc;
+    HIP_TRY(h, enqueue_plan(plan, h->argtab + ai, h->coop_partials, h->coop_counters, h->dev_err, true,
+                            (h->prm.tuning & 1) != 0, h->stream, h,
+                            fhalf ? NMFKL_T_LONG_F : NMFKL_T_LONG_W, fhalf ? NMFKL_T_FUSED_F : NMFKL_T_FUSED_W));
     h->model = fhalf ? kModelCsc : kModelCsr;
     return NMFKL_OK;
 }
@@ -361,6 +463,7 @@ int nmfkl_params_default(nmfkl_params* p) {
     p->collect_stats = 0;
     p->collect_timings = 0;
     p->tuning = 0;
+    p->bin_shift = 0;
     return NMFKL_OK;
 }
 
@@ -475,10 +578,17 @@ int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_str
             fail(h, NMFKL_E_DEVICE, "occupancy query of the long-segment kernel failed");
             return bail(NMFKL_E_DEVICE);
         }
-        int rc = plan_bins(h, pr.csc_ptr, pr.m, &h->binF);
-        if (rc) return bail(rc);
-        rc = plan_bins(h, pr.csr_ptr, pr.n, &h->binW);
-        if (rc) return bail(rc);
+        h->hptr_csc.resize((size_t)pr.m + 1);
+        h->hptr_csr.resize((size_t)pr.n + 1);
+        CREATE_HIP(hipMemcpy(h->hptr_csc.data(), pr.csc_ptr, h->hptr_csc.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+        CREATE_HIP(hipMemcpy(h->hptr_csr.data(), pr.csr_ptr, h->hptr_csr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+        std::string why_plan;
+        int rc = plan_bins({SegSource{&h->hptr_csc, pr.r, 0}}, h->long_capacity, prm.bin_shift, &h->binF, &why_plan);
+        if (!rc) rc = plan_bins({SegSource{&h->hptr_csr, pr.r, 0}}, h->long_capacity, prm.bin_shift, &h->binW, &why_plan);
+        if (rc) {
+            fail(h, rc, why_plan);
+            return bail(rc);
+        }
         const int groups = std::max(h->binF.max_groups, h->binW.max_groups);
         const int pmax = std::max(h->binF.max_pmax, h->binW.max_pmax);
         // k_sweep_long<true> addresses partials + group * (2 * pmax * kCoopValues) + ...
@@ -487,6 +597,16 @@ int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_str
         CREATE_HIP(dalloc(&h->coop_counters, (size_t)std::max(groups, 1) * std::max(pmax, 1) * kFlagStride));
         CREATE_HIP(dalloc(&h->dev_err, 1));
         CREATE_HIP(hipMemsetAsync(h->dev_err, 0, sizeof(unsigned), h->stream));
+    }
+    {
+        SweepArgs args[kNumArgs];
+        PermJob jobs[kNumJobs];
+        make_args(h, args);
+        make_jobs(h, jobs);
+        CREATE_HIP(dalloc(&h->argtab, kNumArgs));
+        CREATE_HIP(dalloc(&h->jobtab, kNumJobs));
+        CREATE_HIP(hipMemcpy(h->argtab, args, sizeof(args), hipMemcpyHostToDevice));
+        CREATE_HIP(hipMemcpy(h->jobtab, jobs, sizeof(jobs), hipMemcpyHostToDevice));
     }
     CREATE_HIP(hipStreamSynchronize(h->stream));
 #undef CREATE_HIP
@@ -533,14 +653,11 @@ int objective_impl(nmfkl_handle* h, double* D_out, bool carried) {
     if (!h) return fail(nullptr, NMFKL_E_INVAL, "null handle");
     if (!D_out) return fail(h, NMFKL_E_INVAL, "D_out is null");
     const nmfkl_problem& pr = h->prob;
-    unsigned* flags = nullptr;
     // natural-order float64 column sums of W and F: sum over all cells of W^T F = sumW . sumF
-    OrderArg identity{};
-    for (int k = 0; k < pr.r; ++k) identity.ids[k] = k;
-    HIP_TRY(h, launch_permute_colsum(pr.W, pr.n, pr.r, h->Sp, identity, nullptr, nullptr, h->partials, h->sum_blocks, h->stream));
-    HIP_TRY(h, launch_finalize_sums(h->partials, h->sum_blocks, pr.r, h->sums2, h->stream));
-    HIP_TRY(h, launch_permute_colsum(pr.F, pr.m, pr.r, h->Sp, identity, nullptr, nullptr, h->partials, h->sum_blocks, h->stream));
-    HIP_TRY(h, launch_finalize_sums(h->partials, h->sum_blocks, pr.r, h->sums2 + pr.r, h->stream));
+    HIP_TRY(h, launch_permute_jobs(h->jobtab + kJobSumW, 1, h->sum_blocks, 0, nullptr, h->stream));
+    HIP_TRY(h, launch_finalize_jobs(h->jobtab + kJobSumW, 1, pr.r, h->stream));
+    HIP_TRY(h, launch_permute_jobs(h->jobtab + kJobSumF, 1, h->sum_blocks, 0, nullptr, h->stream));
+    HIP_TRY(h, launch_finalize_jobs(h->jobtab + kJobSumF, 1, pr.r, h->stream));
     if (carried && (h->model == kModelCsr || h->model == kModelCsc || h->model == kModelCscFresh)) {
         const bool csr = h->model == kModelCsr;
         const int tm = timer_begin(h, NMFKL_T_MODEL);
@@ -567,7 +684,6 @@ int objective_impl(nmfkl_handle* h, double* D_out, bool carried) {
             return fail(h, NMFKL_E_NONFINITE, "a factor holds NaN or Inf");
         total += sums[k] * sums[pr.r + k];
     }
-    (void)flags;
     if (std::isnan(part)) return fail(h, NMFKL_E_NONFINITE, "objective is NaN");
     *D_out = part + total;
     return NMFKL_OK;
@@ -612,6 +728,394 @@ int nmfkl_destroy(nmfkl_handle* h) {
     hipError_t e = hipStreamSynchronize(h->stream);
     release(h);
     delete h;
+    return e == hipSuccess ? NMFKL_OK : NMFKL_E_DEVICE;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batched problems
+struct nmfkl_batch {
+    std::vector<nmfkl_handle*> hs;
+    nmfkl_params prm{};
+    hipStream_t stream = nullptr;     // the caller's stream
+    hipStream_t cap = nullptr;        // capture stream (non-blocking, default priority)
+    SweepArgs* argtab = nullptr;      // device: [2][nprob], F-half entries then W-half entries
+    PermJob* jobtab = nullptr;        // device: [2][nprob]
+    int perm_blocks[2] = {0, 0};
+    int nsum[2] = {0, 0};
+    BinPlan plan[2];
+    double* coop_partials = nullptr;
+    unsigned* coop_flags = nullptr;
+    size_t coop_partials_n = 0, coop_flags_n = 0;
+    unsigned* dev_err = nullptr;
+    int64_t* t_dev = nullptr;
+    int long_capacity = 0;
+    int graph_coop = -1;
+    std::vector<std::pair<int, hipGraphExec_t>> graphs;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_batch_error;
+
+int bfail(nmfkl_batch* b, int code, const std::string& msg) {
+    if (b) b->err = msg;
+    else g_batch_error = msg;
+    return code;
+}
+
+#define BHIP(b, expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return bfail(b, NMFKL_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+void drop_graphs(nmfkl_batch* b) {
+    for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.second);
+    b->graphs.clear();
+}
+
+void batch_release(nmfkl_batch* b) {
+    drop_graphs(b);
+    free_plan(&b->plan[0]);
+    free_plan(&b->plan[1]);
+    auto f = [](void* p) { if (p) (void)hipFree(p); };
+    f(b->argtab); f(b->jobtab); f(b->coop_partials); f(b->coop_flags); f(b->dev_err); f(b->t_dev);
+    b->argtab = nullptr; b->jobtab = nullptr; b->coop_partials = nullptr; b->coop_flags = nullptr;
+    b->dev_err = nullptr; b->t_dev = nullptr;
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    b->cap = nullptr;
+    for (nmfkl_handle* h : b->hs) nmfkl_destroy(h);
+    b->hs.clear();
+}
+
+// Bins of both halves over all problems under b->prm.bin_shift, and cross-block scratch for
+// their cooperative rounds.
+int batch_plan(nmfkl_batch* b) {
+    drop_graphs(b);
+    free_plan(&b->plan[0]);
+    free_plan(&b->plan[1]);
+    std::vector<SegSource> srcF, srcW;
+    for (size_t p = 0; p < b->hs.size(); ++p) {
+        srcF.push_back(SegSource{&b->hs[p]->hptr_csc, b->hs[p]->prob.r, (int)p});
+        srcW.push_back(SegSource{&b->hs[p]->hptr_csr, b->hs[p]->prob.r, (int)p});
+    }
+    std::string why;
+    int rc = plan_bins(srcF, b->long_capacity, b->prm.bin_shift, &b->plan[0], &why);
+    if (!rc) rc = plan_bins(srcW, b->long_capacity, b->prm.bin_shift, &b->plan[1], &why);
+    if (rc) return bfail(b, rc, why);
+    const int groups = std::max(std::max(b->plan[0].max_groups, b->plan[1].max_groups), 1);
+    const int pmax = std::max(std::max(b->plan[0].max_pmax, b->plan[1].max_pmax), 1);
+    const size_t np = (size_t)groups * 2 * pmax * kCoopValues, nf = (size_t)groups * pmax * kFlagStride;
+    if (np > b->coop_partials_n) {
+        if (b->coop_partials) (void)hipFree(b->coop_partials);
+        b->coop_partials = nullptr;
+        BHIP(b, dalloc(&b->coop_partials, np));
+        b->coop_partials_n = np;
+    }
+    if (nf > b->coop_flags_n) {
+        if (b->coop_flags) (void)hipFree(b->coop_flags);
+        b->coop_flags = nullptr;
+        BHIP(b, dalloc(&b->coop_flags, nf));
+        b->coop_flags_n = nf;
+    }
+    return NMFKL_OK;
+}
+
+// Every problem's model values in CSR order (the order the graph's F-half reads): computed
+// from W and F if none are carried, converted if they are in CSC order.
+int batch_models(nmfkl_batch* b) {
+    for (nmfkl_handle* h : b->hs) {
+        if (h->model == kModelNone) {
+            const int rc = refresh_model(h);
+            if (rc) return bfail(b, rc, h->err);
+        }
+        if (h->model == kModelCsc || h->model == kModelCscFresh) {
+            BHIP(b, launch_gather_f64(h->Mcsc, h->csr2csc, h->prob.nnz, h->Mcsr, b->stream));
+            h->model = kModelCsr;
+        }
+    }
+    return NMFKL_OK;
+}
+
+// nsweeps outer iterations, t = *t_dev + k, on stream s.
+hipError_t batch_enqueue(nmfkl_batch* b, hipStream_t s, int nsweeps, bool cooperative) {
+    const int np = (int)b->hs.size();
+    const bool la = (b->prm.tuning & 1) != 0;
+    hipError_t e;
+    for (int k = 0; k < nsweeps; ++k)
+        for (int half = 0; half < 2; ++half) {
+            const PermJob* jobs = b->jobtab + (size_t)half * np;
+            if ((e = launch_permute_jobs(jobs, np, b->perm_blocks[half], k, b->t_dev, s)) != hipSuccess) return e;
+            if ((e = launch_finalize_jobs(jobs, np, b->nsum[half], s)) != hipSuccess) return e;
+            if ((e = enqueue_plan(b->plan[half], b->argtab + (size_t)half * np, b->coop_partials, b->coop_flags,
+                                  b->dev_err, cooperative, la, s, nullptr, 0, 0)) != hipSuccess)
+                return e;
+        }
+    return hipSuccess;
+}
+
+hipError_t batch_capture(nmfkl_batch* b, int nsweeps, bool cooperative, hipGraphExec_t* exec) {
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const hipError_t ee = batch_enqueue(b, b->cap, nsweeps, cooperative);
+    e = hipStreamEndCapture(b->cap, &g);
+    if (ee != hipSuccess || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return ee != hipSuccess ? ee : e;
+    }
+    e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* nmfkl_batch_last_error(const nmfkl_batch* b) { return b ? b->err.c_str() : g_batch_error.c_str(); }
+
+int nmfkl_batch_create(int32_t nprob, const nmfkl_problem* probs, const nmfkl_params* p, void* hip_stream,
+                       nmfkl_batch** out) {
+    if (!out) return bfail(nullptr, NMFKL_E_INVAL, "out is null");
+    *out = nullptr;
+    if (nprob < 1 || nprob > 65536) return bfail(nullptr, NMFKL_E_INVAL, "nprob must be in [1, 65536]");
+    if (!probs) return bfail(nullptr, NMFKL_E_INVAL, "probs is null");
+    nmfkl_params prm;
+    if (p) prm = *p;
+    else nmfkl_params_default(&prm);
+    std::string why;
+    if (check_params(&prm, &why)) return bfail(nullptr, NMFKL_E_INVAL, why);
+    nmfkl_batch* b = new (std::nothrow) nmfkl_batch();
+    if (!b) return bfail(nullptr, NMFKL_E_NOMEM, "host allocation failed");
+    b->prm = prm;
+    b->prm.collect_timings = 0;
+    b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    auto bail = [&](int code) {
+        g_batch_error = b->err;
+        if (b->stream) (void)hipStreamSynchronize(b->stream);
+        batch_release(b);
+        delete b;
+        return code;
+    };
+    for (int32_t q = 0; q < nprob; ++q) {
+        nmfkl_handle* h = nullptr;
+        const int rc = nmfkl_create(&probs[q], &b->prm, hip_stream, &h);
+        if (rc) {
+            bfail(b, rc, "problem " + std::to_string(q) + ": " + nmfkl_last_error(nullptr));
+            return bail(rc);
+        }
+        b->hs.push_back(h);
+    }
+    b->long_capacity = b->hs[0]->long_capacity;
+    std::vector<SweepArgs> args(2 * (size_t)nprob);
+    std::vector<PermJob> jobs(2 * (size_t)nprob);
+    for (int half = 0; half < 2; ++half) {
+        int first_block = 0, first_sum = 0;
+        for (int32_t q = 0; q < nprob; ++q) {
+            nmfkl_handle* h = b->hs[q];
+            SweepArgs a[kNumArgs];
+            PermJob j[kNumJobs];
+            make_args(h, a);
+            make_jobs(h, j);
+            args[(size_t)half * nprob + q] = a[half == 0 ? kArgFfromCsr : kArgWfromCsc];
+            PermJob jb = j[half == 0 ? kJobF : kJobW];
+            jb.first_block = first_block;
+            jb.first_sum = first_sum;
+            first_block += jb.nblocks;
+            first_sum += jb.r;
+            jobs[(size_t)half * nprob + q] = jb;
+        }
+        b->perm_blocks[half] = first_block;
+        b->nsum[half] = first_sum;
+    }
+    auto dev = [&](hipError_t e, const char* what) {
+        bfail(b, NMFKL_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+        return bail(NMFKL_E_DEVICE);
+    };
+    hipError_t e;
+    if ((e = dalloc(&b->argtab, args.size())) != hipSuccess) return dev(e, "allocation");
+    if ((e = dalloc(&b->jobtab, jobs.size())) != hipSuccess) return dev(e, "allocation");
+    if ((e = hipMemcpy(b->argtab, args.data(), args.size() * sizeof(SweepArgs), hipMemcpyHostToDevice)) != hipSuccess)
+        return dev(e, "table upload");
+    if ((e = hipMemcpy(b->jobtab, jobs.data(), jobs.size() * sizeof(PermJob), hipMemcpyHostToDevice)) != hipSuccess)
+        return dev(e, "table upload");
+    if ((e = dalloc(&b->dev_err, 1)) != hipSuccess) return dev(e, "allocation");
+    if ((e = dalloc(&b->t_dev, 1)) != hipSuccess) return dev(e, "allocation");
+    if ((e = hipMemsetAsync(b->dev_err, 0, sizeof(unsigned), b->stream)) != hipSuccess) return dev(e, "memset");
+    if ((e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) != hipSuccess) return dev(e, "stream");
+    const int rc = batch_plan(b);
+    if (rc) return bail(rc);
+    if ((e = hipStreamSynchronize(b->stream)) != hipSuccess) return dev(e, "synchronize");
+    *out = b;
+    return NMFKL_OK;
+}
+
+int nmfkl_batch_run(nmfkl_batch* b, int32_t t0, int32_t nsweeps) {
+    if (!b) return bfail(nullptr, NMFKL_E_INVAL, "null batch");
+    if (t0 < 0) return bfail(b, NMFKL_E_INVAL, "t0 must be >= 0");
+    if (nsweeps < 1 || nsweeps > 100000) return bfail(b, NMFKL_E_INVAL, "nsweeps must be in [1, 100000]");
+    int rc = batch_models(b);
+    if (rc) return rc;
+    hipGraphExec_t exec = nullptr;
+    for (auto& g : b->graphs)
+        if (g.first == nsweeps) exec = g.second;
+    if (!exec) {
+        // the capture stream must see the model work already enqueued on the caller's stream
+        // only through the graph launch's stream order, so nothing else is needed here
+        hipError_t e = hipErrorUnknown;
+        if (b->graph_coop != 0) {
+            e = batch_capture(b, nsweeps, true, &exec);
+            if (e == hipSuccess) b->graph_coop = 1;
+        }
+        if (e != hipSuccess) {
+            exec = nullptr;
+            e = batch_capture(b, nsweeps, false, &exec);
+            if (e != hipSuccess) return bfail(b, NMFKL_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+            b->graph_coop = 0;
+        }
+        b->graphs.emplace_back(nsweeps, exec);
+    }
+    BHIP(b, launch_set_i64(b->t_dev, t0, b->stream));
+    BHIP(b, hipGraphLaunch(exec, b->stream));
+    for (nmfkl_handle* h : b->hs) h->model = kModelCsr;
+    return NMFKL_OK;
+}
+
+int nmfkl_batch_objective(nmfkl_batch* b, double* D_out) {
+    if (!b) return bfail(nullptr, NMFKL_E_INVAL, "null batch");
+    if (!D_out) return bfail(b, NMFKL_E_INVAL, "D_out is null");
+    unsigned derr = 0;
+    BHIP(b, hipMemcpyAsync(&derr, b->dev_err, sizeof(unsigned), hipMemcpyDeviceToHost, b->stream));
+    BHIP(b, hipStreamSynchronize(b->stream));
+    if (derr) return bfail(b, NMFKL_E_DEVICE, "a cross-block wait of a long segment timed out");
+    for (size_t q = 0; q < b->hs.size(); ++q) {
+        const int rc = objective_impl(b->hs[q], D_out + q, true);
+        if (rc) return bfail(b, rc, "problem " + std::to_string(q) + ": " + b->hs[q]->err);
+    }
+    return NMFKL_OK;
+}
+
+int nmfkl_batch_tune(nmfkl_batch* b, int32_t t, nmfkl_params* chosen) {
+    if (!b) return bfail(nullptr, NMFKL_E_INVAL, "null batch");
+    if (t < 0) return bfail(b, NMFKL_E_INVAL, "t must be >= 0");
+    int rc = batch_models(b);
+    if (rc) return rc;
+    // saved state: W, F and the CSR-order model values of every problem
+    struct Saved { float* W = nullptr; float* F = nullptr; double* M = nullptr; };
+    std::vector<Saved> sv(b->hs.size());
+    auto free_saved = [&]() {
+        for (auto& x : sv) {
+            if (x.W) (void)hipFree(x.W);
+            if (x.F) (void)hipFree(x.F);
+            if (x.M) (void)hipFree(x.M);
+            x = Saved{};
+        }
+    };
+    auto copy_all = [&](bool save) -> hipError_t {
+        hipError_t e;
+        for (size_t q = 0; q < b->hs.size(); ++q) {
+            const nmfkl_problem& pr = b->hs[q]->prob;
+            const size_t nw = (size_t)pr.n * pr.r * sizeof(float), nf = (size_t)pr.m * pr.r * sizeof(float);
+            const size_t nm = (size_t)pr.nnz * sizeof(double);
+            if (save) {
+                if ((e = hipMemcpyAsync(sv[q].W, pr.W, nw, hipMemcpyDeviceToDevice, b->stream)) != hipSuccess) return e;
+                if ((e = hipMemcpyAsync(sv[q].F, pr.F, nf, hipMemcpyDeviceToDevice, b->stream)) != hipSuccess) return e;
+                if (nm && (e = hipMemcpyAsync(sv[q].M, b->hs[q]->Mcsr, nm, hipMemcpyDeviceToDevice, b->stream)) != hipSuccess)
+                    return e;
+            } else {
+                if ((e = hipMemcpyAsync(pr.W, sv[q].W, nw, hipMemcpyDeviceToDevice, b->stream)) != hipSuccess) return e;
+                if ((e = hipMemcpyAsync(pr.F, sv[q].F, nf, hipMemcpyDeviceToDevice, b->stream)) != hipSuccess) return e;
+                if (nm && (e = hipMemcpyAsync(b->hs[q]->Mcsr, sv[q].M, nm, hipMemcpyDeviceToDevice, b->stream)) != hipSuccess)
+                    return e;
+            }
+        }
+        return hipSuccess;
+    };
+    for (size_t q = 0; q < b->hs.size(); ++q) {
+        const nmfkl_problem& pr = b->hs[q]->prob;
+        hipError_t e = dalloc(&sv[q].W, (size_t)pr.n * pr.r);
+        if (e == hipSuccess) e = dalloc(&sv[q].F, (size_t)pr.m * pr.r);
+        if (e == hipSuccess) e = dalloc(&sv[q].M, (size_t)pr.nnz);
+        if (e != hipSuccess) {
+            free_saved();
+            return bfail(b, NMFKL_E_NOMEM, "no device memory for the tuner's saved state");
+        }
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const nmfkl_params orig = b->prm;
+    int best_shift = orig.bin_shift, best_tuning = orig.tuning;
+    float best_ms = 0.0f;
+    bool have = false;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = copy_all(true);
+    for (int shift = 0; shift <= 2 && e == hipSuccess && rc == NMFKL_OK; ++shift)
+        for (int la = 0; la <= 1 && e == hipSuccess && rc == NMFKL_OK; ++la) {
+            b->prm.bin_shift = shift;
+            b->prm.tuning = (orig.tuning & ~1) | la;
+            rc = batch_plan(b);
+            if (rc) break;
+            float ms = 0.0f;
+            for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // the first run warms caches up
+                if ((e = launch_set_i64(b->t_dev, t, b->stream)) != hipSuccess) break;
+                if ((e = hipEventRecord(e0, b->stream)) != hipSuccess) break;
+                if ((e = batch_enqueue(b, b->stream, 1, true)) != hipSuccess) break;
+                if ((e = hipEventRecord(e1, b->stream)) != hipSuccess) break;
+                if ((e = copy_all(false)) != hipSuccess) break;
+                if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+                if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+            }
+            if (e == hipSuccess && (!have || ms < best_ms)) {
+                have = true;
+                best_ms = ms;
+                best_shift = shift;
+                best_tuning = b->prm.tuning;
+            }
+        }
+    hipError_t es = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess) e = es;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    free_saved();
+    b->prm.bin_shift = have ? best_shift : orig.bin_shift;
+    b->prm.tuning = have ? best_tuning : orig.tuning;
+    const int rc2 = batch_plan(b);
+    if (e != hipSuccess) return bfail(b, NMFKL_E_DEVICE, std::string("tuner: ") + hipGetErrorString(e));
+    if (rc) return rc;
+    if (rc2) return rc2;
+    unsigned derr = 0;
+    BHIP(b, hipMemcpy(&derr, b->dev_err, sizeof(unsigned), hipMemcpyDeviceToHost));
+    if (derr) return bfail(b, NMFKL_E_DEVICE, "a cross-block wait of a long segment timed out");
+    if (chosen) *chosen = b->prm;
+    return NMFKL_OK;
+}
+
+int nmfkl_batch_get_info(nmfkl_batch* b, nmfkl_batch_info* out) {
+    if (!b) return bfail(nullptr, NMFKL_E_INVAL, "null batch");
+    if (!out) return bfail(b, NMFKL_E_INVAL, "out is null");
+    std::memset(out, 0, sizeof(*out));
+    out->nprob = (int32_t)b->hs.size();
+    out->bin_shift = b->prm.bin_shift;
+    out->tuning = b->prm.tuning;
+    out->graph_cooperative = b->graph_coop;
+    for (int half = 0; half < 2; ++half) {
+        out->fused_blocks[half] = b->plan[half].nblocks;
+        out->long_single_blocks[half] = b->plan[half].single_blocks;
+        out->long_rounds[half] = (int32_t)b->plan[half].rounds.size();
+    }
+    for (nmfkl_handle* h : b->hs) out->nnz_total += h->prob.nnz;
+    return NMFKL_OK;
+}
+
+int nmfkl_batch_destroy(nmfkl_batch* b) {
+    if (!b) return NMFKL_E_INVAL;
+    const hipError_t e = hipStreamSynchronize(b->stream);
+    batch_release(b);
+    delete b;
     return e == hipSuccess ? NMFKL_OK : NMFKL_E_DEVICE;
 }
 

@@ -319,10 +319,21 @@ int nmfkl_model_create(const float* W, int32_t n, int32_t r, const nmfkl_params*
     const int blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, n / 64));
     double* partials = nullptr;
     CM(hipMalloc(reinterpret_cast<void**>(&partials), sizeof(double) * blocks * r));
-    OrderArg identity{};
-    for (int k = 0; k < r; ++k) identity.ids[k] = k;
-    CM(launch_permute_colsum(W, n, r, r, identity, nullptr, nullptr, partials, blocks, m->stream));
-    CM(launch_finalize_sums(partials, blocks, r, m->sumW, m->stream));
+    PermJob job{};
+    job.A = W;
+    job.partials = partials;
+    job.sums = m->sumW;
+    job.P = n;
+    job.rpb = (n + blocks - 1) / blocks;
+    job.r = r;
+    job.Sp = r;
+    job.nblocks = blocks;
+    job.identity = 1;
+    PermJob* djob = nullptr;
+    CM(hipMalloc(reinterpret_cast<void**>(&djob), sizeof(PermJob)));
+    CM(hipMemcpyAsync(djob, &job, sizeof(PermJob), hipMemcpyHostToDevice, m->stream));
+    CM(launch_permute_jobs(djob, 1, blocks, 0, nullptr, m->stream));
+    CM(launch_finalize_jobs(djob, 1, r, m->stream));
     CM(launch_row_sums(W, n, r, m->rowsumW, m->stream));
     std::vector<double> sw(r);
     CM(hipMemcpyAsync(sw.data(), m->sumW, sizeof(double) * r, hipMemcpyDeviceToHost, m->stream));
@@ -335,6 +346,7 @@ int nmfkl_model_create(const float* W, int32_t n, int32_t r, const nmfkl_params*
     CM(hipMemsetAsync(m->stats, 0, sizeof(unsigned long long) * 6, m->stream));
     CM(hipStreamSynchronize(m->stream));
     (void)hipFree(partials);
+    (void)hipFree(djob);
     m->totW = 0.0;
     for (int k = 0; k < r; ++k) m->totW += sw[k];
 #undef CM

@@ -64,12 +64,27 @@ __host__ __device__ inline void coordinate_order(uint64_t seed, uint64_t t, uint
     }
 }
 
-// A coordinate order passed by value to a kernel.
-struct OrderArg {
-    int32_t ids[NMFKL_R_MAX];
+// One permuted-copy / column-sum job: the fixed factor A (P x r) of one problem's half, or
+// a factor of the objective in its natural order.  Jobs of a launch cover consecutive block
+// ranges [first_block, first_block + nblocks) of the permute launch and [first_sum,
+// first_sum + r) of the finalize launch.
+struct PermJob {
+    const float* A;       // P x r, point-major
+    float* Ap;            // permuted copy, row stride Sp (nullptr: sums only)
+    double* partials;     // nblocks x r float64 partial sums
+    double* sums;         // r column sums (permuted order), written by the finalize launch
+    int32_t* ids;         // the order used, stored by the job's first block (nullptr: not stored)
+    int64_t P;
+    int64_t rpb;          // rows per block
+    uint64_t seed;        // Philox key of the order
+    uint64_t stream;      // Philox stream of the order
+    int32_t r, Sp;
+    int32_t first_block, nblocks;
+    int32_t first_sum;
+    int32_t identity;     // 1: natural order, 0: the order of (seed, t, stream)
 };
 
-// One half-sweep's per-launch arguments.
+// One half-sweep's per-launch arguments (kernels read them from a device table).
 struct SweepArgs {
     const int64_t* ptr;     // segment pointers (CSC for the F-half, CSR for the W-half)
     const int32_t* idx;     // point ids of the nonzeros
@@ -106,16 +121,17 @@ struct FoldinArgs {
     double tol;
 };
 
-// Fold-in variants: 0: 16 lanes x 4, 1: 64 x 4, 2: 256 x 4, 3: 256 x 8 nonzeros.
-constexpr int kFoldinVariants = 4;
-constexpr int kFoldinCapacity[kFoldinVariants] = {64, 256, 1024, 2048};
+// Fold-in variants: 0: 16 lanes x 4, 1: 64 x 4, 2: 256 x 4, 3: 256 x 8 nonzeros (blocks of
+// 256 threads), 4: 512 lanes x 10 nonzeros (one document per 512-thread block).
+constexpr int kFoldinVariants = 5;
+constexpr int kFoldinCapacity[kFoldinVariants] = {64, 256, 1024, 2048, 5120};
 
 // A block of the fused binned launch: variant and its slice of the segment list.
 struct BlockWork {
     int32_t variant;   // index into the (lanes per segment, elements per lane) table
     int32_t first;     // first entry in the segment list
     int32_t count;     // number of segments for this block
-    int32_t pad;
+    int32_t prob;      // entry of the argument table (problem of a batch)
 };
 
 // The (G lanes per segment, E elements per lane) variants of the fused launch.
@@ -137,20 +153,24 @@ struct LongWork {
     int32_t part;   // this block's part, 0 <= part < B
     int32_t B;      // blocks cooperating on the segment
     int32_t group;  // index of the segment's reduction slot in this launch
+    int32_t prob;   // entry of the argument table (problem of a batch)
+    int32_t pad;
 };
 
 // Launch wrappers (defined with the kernels).  All enqueue on `stream`.
-hipError_t launch_permute_colsum(const float* A, int64_t P, int r, int Sp, const OrderArg& order,
-                                 int32_t* ids_out, float* Ap, double* partials, int nblocks,
-                                 hipStream_t stream);
+// Permuted copies and partial column sums of njobs jobs (nblocks = total permute blocks).
+// The order of outer iteration t = t_arg + (t_dev ? *t_dev : 0) is computed on the device.
+hipError_t launch_permute_jobs(const PermJob* jobs, int njobs, int nblocks, int64_t t_arg,
+                               const int64_t* t_dev, hipStream_t stream);
+// Column sums of njobs jobs from their partials (nsum = total of the jobs' r).
+hipError_t launch_finalize_jobs(const PermJob* jobs, int njobs, int nsum, hipStream_t stream);
 hipError_t launch_model_terms(const double* M, const float* val, int64_t nnz, double* partials,
                               int nblocks, hipStream_t stream);
-hipError_t launch_finalize_sums(const double* partials, int nblocks, int r, double* out,
-                                hipStream_t stream);
-hipError_t launch_sweep_fused(const SweepArgs& a, const BlockWork* work, const int32_t* segs,
+// tab: device table of SweepArgs; each block uses tab[work.prob].
+hipError_t launch_sweep_fused(const SweepArgs* tab, const BlockWork* work, const int32_t* segs,
                               int nblocks, bool lookahead, hipStream_t stream);
 // Long segments that fit one block (B = 1): ordinary launch.
-hipError_t launch_sweep_long_single(const SweepArgs& a, const LongWork* work, int nblocks,
+hipError_t launch_sweep_long_single(const SweepArgs* tab, const LongWork* work, int nblocks,
                                     hipStream_t stream);
 // Partial sums a cooperating block publishes per reduction (S1 and S2 of every chunk
 // coordinate).
@@ -160,8 +180,10 @@ constexpr int kFlagStride = 32;
 // Cooperative launch over long segments; zeroes the arrival flags first.  partials holds
 // 2 * pmax * kCoopValues doubles and flags pmax * kFlagStride words per group (pmax =
 // largest B in the launch).
-hipError_t launch_sweep_long(const SweepArgs& a, const LongWork* work, int nblocks, double* partials,
-                             unsigned* flags, int ngroups, unsigned* err, int pmax,
+// cooperative = false: ordinary launch of the same grid (inside a captured graph), which
+// relies on the grid fitting the device's co-resident capacity; the waits stay bounded.
+hipError_t launch_sweep_long(const SweepArgs* tab, const LongWork* work, int nblocks, double* partials,
+                             unsigned* flags, int ngroups, unsigned* err, int pmax, bool cooperative,
                              hipStream_t stream);
 // Co-resident blocks of the long-segment kernel per compute unit (0 on failure).
 int long_kernel_blocks_per_cu();
@@ -169,6 +191,11 @@ hipError_t launch_model_objective(const int64_t* csc_ptr, const int32_t* csc_idx
                                   const float* csc_val, int m, const float* W, const float* F, int r,
                                   double* Mcsc, double* partials, int nblocks, hipStream_t stream);
 hipError_t launch_sum_f64(const double* in, int count, double* out, hipStream_t stream);
+// dst[q] = src[map[q]], q < count.
+hipError_t launch_gather_f64(const double* src, const int32_t* map, int64_t count, double* dst,
+                             hipStream_t stream);
+// *p = v (a kernel, so that it can precede a graph launch without a host-memory copy).
+hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t stream);
 hipError_t launch_validate_ptr(const int64_t* ptr, int64_t Q, int64_t nnz, unsigned* flags,
                                hipStream_t stream);
 hipError_t launch_validate_entries(const int64_t* ptr, const int32_t* idx, const float* val,

@@ -19,6 +19,8 @@
 // example when the other coordinates of a one-nonzero column drop to zero): in float32 the
 // rounding error of the starting value would then become a large relative error of the
 // small remainder, and with it of the derivatives.
+#include <algorithm>
+
 #include "nmfkl_internal.hpp"
 
 namespace nmfkl {
@@ -55,75 +57,117 @@ __device__ __forceinline__ float group_sum(float v) {
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // ------------------------------------------------- permuted copy + float64 column sums
-// The coordinate order arrives by value (computed on the host from the same Philox
-// definition); block 0 also stores it for the sweep kernels.  Block b covers rows
-// [b*rpb, (b+1)*rpb).  Thread (ry, cx) walks rows ry, ry+4, ... of the block for permuted
-// column s = s0 + cx, reading A[p][ids[s]] and writing Ap[p][s] (zero in the padding).
-// Per-block float64 partial sums go to partials[b*r + s]; k_finalize_sums adds them in a
-// fixed order, so the result is deterministic.
-__global__ void __launch_bounds__(256) k_permute_colsum(const float* __restrict__ A, int64_t P,
-                                                        int r, int Sp, OrderArg order,
-                                                        int32_t* __restrict__ ids_out,
-                                                        float* __restrict__ Ap,
-                                                        double* __restrict__ partials,
-                                                        int64_t rpb) {
-    __shared__ int32_t sid[NMFKL_R_MAX];
-    __shared__ double red[4][64];
-    for (int s = threadIdx.x; s < NMFKL_R_MAX; s += 256) sid[s] = s < r ? order.ids[s] : -1;
-    if (ids_out && blockIdx.x == 0)
-        for (int s = threadIdx.x; s < r; s += 256) ids_out[s] = order.ids[s];
+// Job of a block: the last job whose first index is <= b (jobs in increasing order).
+template <class Key>
+__device__ __forceinline__ int find_job(const PermJob* jobs, int njobs, int b, Key key) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (key(jobs[mid]) <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// The job's coordinate order into sid[0..NMFKL_R_MAX) (-1 beyond r): the Fisher-Yates
+// shuffle of coordinate_order, with its Philox blocks computed by parallel threads (block q
+// gives words 4q..4q+3; step i = r-1, ..., 1 uses word r-1-i) and the swaps by thread 0.
+__device__ void job_order(const PermJob& jb, int64_t t, int32_t* sid, uint64_t* words) {
+    const int r = jb.r;
+    if (jb.identity) {
+        for (int s = threadIdx.x; s < NMFKL_R_MAX; s += blockDim.x) sid[s] = s < r ? s : -1;
+        __syncthreads();
+        return;
+    }
+    const int nblk = (r - 1 + 3) / 4;
+    for (int q = threadIdx.x; q < nblk; q += blockDim.x) {
+        const uint64_t ctr[4] = {(uint64_t)q, (uint64_t)t, jb.stream, 0};
+        const uint64_t key[2] = {jb.seed, 0};
+        uint64_t out[4];
+        philox4x64_10(ctr, key, out);
+        for (int k = 0; k < 4; ++k) words[4 * q + k] = out[k];
+    }
+    for (int s = threadIdx.x; s < NMFKL_R_MAX; s += blockDim.x) sid[s] = s < r ? s : -1;
     __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = r - 1; i >= 1; --i) {
+            const int j = (int)__umul64hi(words[r - 1 - i], (uint64_t)(i + 1));
+            const int32_t tmp = sid[i];
+            sid[i] = sid[j];
+            sid[j] = tmp;
+        }
+    }
+    __syncthreads();
+}
+
+// Block b of job j covers rows [lb*rpb, (lb+1)*rpb), lb = b - first_block.  Thread (ry, cx)
+// walks rows ry, ry+4, ... for permuted column s = s0 + cx, reading A[p][ids[s]] and
+// writing Ap[p][s] (zero in the padding).  Per-block float64 partial sums go to
+// partials[lb*r + s]; k_finalize_jobs adds them in a fixed order, so the result is
+// deterministic.  The job's first block also stores the order for the sweep kernels.
+__global__ void __launch_bounds__(256) k_permute_jobs(const PermJob* __restrict__ jobs, int njobs,
+                                                      int64_t t_arg, const int64_t* __restrict__ t_dev) {
+    __shared__ int32_t sid[NMFKL_R_MAX];
+    __shared__ uint64_t words[NMFKL_R_MAX];
+    __shared__ double red[4][64];
+    const int jj = find_job(jobs, njobs, (int)blockIdx.x, [](const PermJob& q) { return q.first_block; });
+    const PermJob jb = jobs[jj];
+    const int64_t lb = (int64_t)blockIdx.x - jb.first_block;
+    const int64_t t = t_arg + (t_dev ? *t_dev : 0);
+    job_order(jb, t, sid, words);
+    const int r = jb.r, Sp = jb.Sp;
+    if (jb.ids && lb == 0)
+        for (int s = threadIdx.x; s < r; s += 256) jb.ids[s] = sid[s];
     const int cx = threadIdx.x & 63, ry = threadIdx.x >> 6;
-    const int64_t p0 = (int64_t)blockIdx.x * rpb;
-    const int64_t p1 = p0 + rpb < P ? p0 + rpb : P;
+    const int64_t p0 = lb * jb.rpb;
+    const int64_t p1 = p0 + jb.rpb < jb.P ? p0 + jb.rpb : jb.P;
     for (int s0 = 0; s0 < Sp; s0 += 64) {
         const int s = s0 + cx;
         const int k = s < Sp ? sid[s] : -1;
         double acc = 0.0;
         if (s < Sp) {
             for (int64_t p = p0 + ry; p < p1; p += 4) {
-                const float a = k >= 0 ? A[p * r + k] : 0.0f;
-                if (Ap) Ap[p * Sp + s] = a;
+                const float a = k >= 0 ? jb.A[p * r + k] : 0.0f;
+                if (jb.Ap) jb.Ap[p * Sp + s] = a;
                 acc += (double)a;
             }
         }
         red[ry][cx] = acc;
         __syncthreads();
         if (ry == 0 && s < r)
-            partials[(int64_t)blockIdx.x * r + s] = ((red[0][cx] + red[1][cx]) + red[2][cx]) + red[3][cx];
+            jb.partials[lb * r + s] = ((red[0][cx] + red[1][cx]) + red[2][cx]) + red[3][cx];
         __syncthreads();
     }
 }
 
-hipError_t launch_permute_colsum(const float* A, int64_t P, int r, int Sp, const OrderArg& order,
-                                 int32_t* ids_out, float* Ap, double* partials, int nblocks,
-                                 hipStream_t stream) {
-    const int64_t rpb = (P + nblocks - 1) / nblocks;
-    hipLaunchKernelGGL(k_permute_colsum, dim3(nblocks), dim3(256), 0, stream, A, P, r, Sp, order,
-                       ids_out, Ap, partials, rpb);
+hipError_t launch_permute_jobs(const PermJob* jobs, int njobs, int nblocks, int64_t t_arg,
+                               const int64_t* t_dev, hipStream_t stream) {
+    if (njobs <= 0 || nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_permute_jobs, dim3(nblocks), dim3(256), 0, stream, jobs, njobs, t_arg, t_dev);
     return hipGetLastError();
 }
 
-// One block per column s: the block's threads add the per-block partials b = t, t+256, ...
-// and a fixed tree combines them.
-__global__ void __launch_bounds__(256) k_finalize_sums(const double* __restrict__ partials,
-                                                       int nblocks, int r, double* __restrict__ out) {
+// Block b = (job j, column s = b - first_sum): the block's threads add the job's per-block
+// partials q = t, t+256, ... and a fixed tree combines them.
+__global__ void __launch_bounds__(256) k_finalize_jobs(const PermJob* __restrict__ jobs, int njobs) {
     __shared__ double red[256];
-    const int s = blockIdx.x;
+    const int jj = find_job(jobs, njobs, (int)blockIdx.x, [](const PermJob& q) { return q.first_sum; });
+    const PermJob& jb = jobs[jj];
+    const int s = (int)blockIdx.x - jb.first_sum;
     double acc = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += 256) acc += partials[(int64_t)b * r + s];
+    for (int b = threadIdx.x; b < jb.nblocks; b += 256) acc += jb.partials[(int64_t)b * jb.r + s];
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[s] = red[0];
+    if (threadIdx.x == 0) jb.sums[s] = red[0];
 }
 
-hipError_t launch_finalize_sums(const double* partials, int nblocks, int r, double* out,
-                                hipStream_t stream) {
-    hipLaunchKernelGGL(k_finalize_sums, dim3(r), dim3(256), 0, stream, partials, nblocks, r, out);
+hipError_t launch_finalize_jobs(const PermJob* jobs, int njobs, int nsum, hipStream_t stream) {
+    if (njobs <= 0 || nsum <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finalize_jobs, dim3(nsum), dim3(256), 0, stream, jobs, njobs);
     return hipGetLastError();
 }
 
@@ -603,10 +647,12 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const BlockWork&
 // LA256 selects the lookahead form for the 256-lane variant.
 template <bool LA256>
 __global__ void __launch_bounds__(kFusedThreads, 2)
-k_sweep_fused(SweepArgs a, const BlockWork* __restrict__ work, const int32_t* __restrict__ segs) {
+k_sweep_fused(const SweepArgs* __restrict__ tab, const BlockWork* __restrict__ work,
+              const int32_t* __restrict__ segs) {
     __shared__ float xs_all[(kFusedThreads / 8) * NMFKL_R_MAX];
     __shared__ float red[2 * (kFusedThreads / 64) * kMaxRed];
     const BlockWork wk = work[blockIdx.x];
+    const SweepArgs a = tab[wk.prob];
     switch (wk.variant) {
         case 0: sweep_block<8, 4, false>(a, wk, segs, xs_all, red); break;
         case 1: sweep_block<16, 4, false>(a, wk, segs, xs_all, red); break;
@@ -616,13 +662,13 @@ k_sweep_fused(SweepArgs a, const BlockWork* __restrict__ work, const int32_t* __
     }
 }
 
-hipError_t launch_sweep_fused(const SweepArgs& a, const BlockWork* work, const int32_t* segs,
+hipError_t launch_sweep_fused(const SweepArgs* tab, const BlockWork* work, const int32_t* segs,
                               int nblocks, bool lookahead, hipStream_t stream) {
     if (nblocks <= 0) return hipSuccess;
     if (lookahead)
-        hipLaunchKernelGGL(k_sweep_fused<true>, dim3(nblocks), dim3(kFusedThreads), 0, stream, a, work, segs);
+        hipLaunchKernelGGL(k_sweep_fused<true>, dim3(nblocks), dim3(kFusedThreads), 0, stream, tab, work, segs);
     else
-        hipLaunchKernelGGL(k_sweep_fused<false>, dim3(nblocks), dim3(kFusedThreads), 0, stream, a, work, segs);
+        hipLaunchKernelGGL(k_sweep_fused<false>, dim3(nblocks), dim3(kFusedThreads), 0, stream, tab, work, segs);
     return hipGetLastError();
 }
 
@@ -633,8 +679,9 @@ hipError_t launch_sweep_fused(const SweepArgs& a, const BlockWork* work, const i
 // every wait ends.
 template <bool COOP>
 __global__ void __launch_bounds__(kLongThreads, 2)
-k_sweep_long(SweepArgs a, const LongWork* __restrict__ work, double* __restrict__ partials,
-             unsigned* __restrict__ flags, unsigned* __restrict__ err, int pmax) {
+k_sweep_long(const SweepArgs* __restrict__ tab, const LongWork* __restrict__ work,
+             double* __restrict__ partials, unsigned* __restrict__ flags, unsigned* __restrict__ err,
+             int pmax) {
     __shared__ float xs[NMFKL_R_MAX];
     __shared__ float red_lds[2 * (kLongThreads / 64) * kMaxRed];
     __shared__ double tmp[(kLongThreads / kMaxRed) * kMaxRed];
@@ -642,6 +689,7 @@ k_sweep_long(SweepArgs a, const LongWork* __restrict__ work, double* __restrict_
     __shared__ int32_t s_id[kLongCapacity];
     __shared__ float s_v[kLongCapacity], s_w[kLongCapacity], s_u[kLongCapacity];
     const LongWork wk = work[blockIdx.x];
+    const SweepArgs a = tab[wk.prob];
     const int lane = threadIdx.x;
     LdsElems<kLongE, kLongThreads> st;
     st.idp = s_id + lane;
@@ -678,24 +726,28 @@ __global__ void k_zero_u32(unsigned* p, int n) {
     if (i < n) p[i] = 0u;
 }
 
-hipError_t launch_sweep_long_single(const SweepArgs& a, const LongWork* work, int nblocks,
+hipError_t launch_sweep_long_single(const SweepArgs* tab, const LongWork* work, int nblocks,
                                     hipStream_t stream) {
     if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sweep_long<false>, dim3(nblocks), dim3(kLongThreads), 0, stream, a, work,
+    hipLaunchKernelGGL(k_sweep_long<false>, dim3(nblocks), dim3(kLongThreads), 0, stream, tab, work,
                        (double*)nullptr, (unsigned*)nullptr, (unsigned*)nullptr, 0);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_long(const SweepArgs& a, const LongWork* work, int nblocks, double* partials,
-                             unsigned* flags, int ngroups, unsigned* err, int pmax,
+hipError_t launch_sweep_long(const SweepArgs* tab, const LongWork* work, int nblocks, double* partials,
+                             unsigned* flags, int ngroups, unsigned* err, int pmax, bool cooperative,
                              hipStream_t stream) {
     if (nblocks <= 0) return hipSuccess;
     const int nflags = ngroups * pmax * kFlagStride;
     hipLaunchKernelGGL(k_zero_u32, dim3((nflags + 255) / 256), dim3(256), 0, stream, flags, nflags);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    SweepArgs aa = a;
-    void* args[] = {&aa, &work, &partials, &flags, &err, &pmax};
+    if (!cooperative) {
+        hipLaunchKernelGGL(k_sweep_long<true>, dim3(nblocks), dim3(kLongThreads), 0, stream, tab, work,
+                           partials, flags, err, pmax);
+        return hipGetLastError();
+    }
+    void* args[] = {&tab, &work, &partials, &flags, &err, &pmax};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_sweep_long<true>), dim3(nblocks),
                                       dim3(kLongThreads), args, 0, stream);
 }
@@ -748,16 +800,16 @@ __device__ __forceinline__ double doc_kl(const FoldinArgs& f, St& st, int lane, 
     return red.sum_f64(acc);
 }
 
-template <int G, int E, bool LA, class Red>
+template <int G, bool LA, class Red, class St>
 __device__ __forceinline__ void foldin_segment(const FoldinArgs& f, const SweepArgs& a, int d, bool active,
-                                               int lane, float* xs, int32_t* perm_lds, Red& red) {
+                                               int lane, float* xs, int32_t* perm_lds, Red& red, St& st) {
+    constexpr int E = St::kE;
     int64_t base = 0;
     int L = 0;
     if (active) {
         base = f.ptr[d];
         L = (int)(f.ptr[d + 1] - base);
     }
-    RegElems<E> st;
     double mass = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -841,14 +893,39 @@ k_foldin(FoldinArgs f, SweepArgs a, const int32_t* __restrict__ docs, int ndocs)
     const int di = blockIdx.x * SPB + slot;
     const bool active = di < ndocs;
     const int d = active ? docs[di] : 0;
+    RegElems<E> st;
     if constexpr (G <= 64) {
         WaveReducer<G> rd;
-        foldin_segment<G, E, true>(f, a, d, active, lane, xs_all + slot * NMFKL_R_MAX,
-                                   perm_all + slot * NMFKL_R_MAX, rd);
+        foldin_segment<G, true>(f, a, d, active, lane, xs_all + slot * NMFKL_R_MAX,
+                                perm_all + slot * NMFKL_R_MAX, rd, st);
     } else {
         BlockReducer<G> rd{red, 0, red64};
-        foldin_segment<G, E, true>(f, a, d, active, lane, xs_all, perm_all, rd);
+        foldin_segment<G, true>(f, a, d, active, lane, xs_all, perm_all, rd, st);
     }
+}
+
+// One document per block of G threads (the longest documents): counts, w, u and word ids in
+// LDS, the model values and the tile chunk in registers.  LA = false evaluates each
+// coordinate's sums on their own (fewer registers; the same sums in the same order).
+template <int G, int E, bool LA>
+__global__ void __launch_bounds__(G)
+k_foldin_block(FoldinArgs f, SweepArgs a, const int32_t* __restrict__ docs, int ndocs) {
+    __shared__ float xs[NMFKL_R_MAX];
+    __shared__ int32_t perm[NMFKL_R_MAX];
+    __shared__ float red[2 * (G / 64) * kMaxRed];
+    __shared__ double red64[2 * (G / 64)];
+    __shared__ int32_t s_id[G * E];
+    __shared__ float s_v[G * E], s_w[G * E], s_u[G * E];
+    const bool active = (int)blockIdx.x < ndocs;
+    const int d = active ? docs[blockIdx.x] : 0;
+    const int lane = threadIdx.x;
+    BlockReducer<G> rd{red, 0, red64};
+    LdsElems<E, G> st;
+    st.idp = s_id + lane;
+    st.vp = s_v + lane;
+    st.wp = s_w + lane;
+    st.up = s_u + lane;
+    foldin_segment<G, LA>(f, a, d, active, lane, xs, perm, rd, st);
 }
 
 hipError_t launch_foldin(const FoldinArgs& f, const SweepArgs& a, int variant, const int32_t* docs,
@@ -864,8 +941,11 @@ hipError_t launch_foldin(const FoldinArgs& f, const SweepArgs& a, int variant, c
         case 2:
             hipLaunchKernelGGL((k_foldin<256, 4>), dim3(ndocs), dim3(kFusedThreads), 0, stream, f, a, docs, ndocs);
             break;
+        case 3:
+            hipLaunchKernelGGL((k_foldin_block<256, 8, true>), dim3(ndocs), dim3(256), 0, stream, f, a, docs, ndocs);
+            break;
         default:
-            hipLaunchKernelGGL((k_foldin<256, 8>), dim3(ndocs), dim3(kFusedThreads), 0, stream, f, a, docs, ndocs);
+            hipLaunchKernelGGL((k_foldin_block<512, 10, false>), dim3(ndocs), dim3(512), 0, stream, f, a, docs, ndocs);
             break;
     }
     return hipGetLastError();
@@ -960,6 +1040,31 @@ __global__ void __launch_bounds__(256) k_model_terms(const double* __restrict__ 
 hipError_t launch_model_terms(const double* M, const float* val, int64_t nnz, double* partials,
                               int nblocks, hipStream_t stream) {
     hipLaunchKernelGGL(k_model_terms, dim3(nblocks), dim3(256), 0, stream, M, val, nnz, partials);
+    return hipGetLastError();
+}
+
+// dst[q] = src[map[q]]: the model values of one storage order in the other.
+__global__ void __launch_bounds__(256) k_gather_f64(const double* __restrict__ src,
+                                                    const int32_t* __restrict__ map, int64_t count,
+                                                    double* __restrict__ dst) {
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < count; q += (int64_t)gridDim.x * 256)
+        dst[q] = src[map[q]];
+}
+
+hipError_t launch_gather_f64(const double* src, const int32_t* map, int64_t count, double* dst,
+                             hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    const int64_t nb = std::min<int64_t>((count + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_gather_f64, dim3((unsigned)nb), dim3(256), 0, stream, src, map, count, dst);
+    return hipGetLastError();
+}
+
+__global__ void k_set_i64(int64_t* p, int64_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t stream) {
+    hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, stream, p, v);
     return hipGetLastError();
 }
 

@@ -270,20 +270,35 @@ def config(i: int, seed: int = 0, **overrides) -> Problem:
     raise ValueError(f"config {i}: use batched_configs() / serving_* for 3 and 4")
 
 
-def batched_configs(seed: int = 0, count: int = 64, scale: float = 1.0):
+def _batched_member(args):
+    n, m, r, dens, seed, p = args
+    ptr, idx, val, Ws, Fs, c = planted(n, m, r, dens, seed, tag=1000 + p)
+    return _problem(n, m, r, ptr, idx, val, seed, 1000 + p,
+                    {"name": f"batched[{p}]", "sweeps": 10, "density": dens})
+
+
+def batched_configs(seed: int = 0, count: int = 64, scale: float = 1.0, workers: int = 1):
     """64 independent planted problems: n ~ U{1k..20k}, m ~ U{1k..50k}, r ~ U{10,16,32,64},
-    density ~ U[0.1%, 2%], planted rank = r.  ``scale`` < 1 shrinks n and m (tests)."""
+    density ~ U[0.1%, 2%], planted rank = r.  ``scale`` < 1 shrinks n and m (tests).
+    ``workers`` > 1 generates the members in forked worker processes (same result; call
+    it before the process uses a GPU)."""
     g = _rng(0xBA7C, seed)
-    out = []
+    specs = []
     for p in range(count):
         n = max(8, int(g.integers(1000, 20001) * scale))
         m = max(8, int(g.integers(1000, 50001) * scale))
         r = int(g.choice([10, 16, 32, 64]))
         dens = float(g.uniform(0.001, 0.02))
-        ptr, idx, val, Ws, Fs, c = planted(n, m, r, dens, seed, tag=1000 + p)
-        out.append(_problem(n, m, r, ptr, idx, val, seed, 1000 + p,
-                            {"name": f"batched[{p}]", "sweeps": 10, "density": dens}))
-    return out
+        specs.append((n, m, r, dens, seed, p))
+    if workers <= 1:
+        return [_batched_member(s) for s in specs]
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    # largest members first, so that the pool's tail is short
+    order = sorted(range(count), key=lambda p: -specs[p][0] * specs[p][1] * specs[p][3])
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        done = dict(zip(order, ex.map(_batched_member, [specs[p] for p in order])))
+    return [done[p] for p in range(count)]
 
 
 def serving_model(n: int = 50_000, r: int = 100, seed: int = 0) -> np.ndarray:

@@ -94,9 +94,9 @@ def test_server_admission_by_memory(small_serving):
     import torch
     W, ptr, idx, val = small_serving
     m = P.nmfkl_model_create(torch.from_numpy(W).cuda())
-    budget = 2048 * 8  # exactly one largest document
+    budget = 5120 * 8  # exactly one largest document
     srv = P.nmfkl_server_create(m, budget, lanes=1, lane_docs=8)
-    big = np.arange(0, 4000, 2, dtype=np.int32)[:2000]
+    big = np.arange(0, 5120, dtype=np.int32)
     ones = np.ones(big.size, np.float32)
     assert P.nmfkl_server_submit(srv, 1, big, ones) == 0
     assert P.nmfkl_server_submit(srv, 2, big[:100], ones[:100]) == -2    # refused: budget full
@@ -110,3 +110,32 @@ def test_server_admission_by_memory(small_serving):
         P.nmfkl_server_submit(srv, 3, np.array([5, 3], np.int32), np.ones(2, np.float32))  # not increasing
     P.nmfkl_server_destroy(srv)
     P.nmfkl_model_destroy(m)
+
+
+def test_long_documents_vs_oracle(small_serving):
+    """Documents of 2049..5120 distinct words (one document per 256- or 512-lane block)."""
+    import torch
+    W, _, _, _ = small_serving
+    n = W.shape[0]
+    g = np.random.default_rng(11)
+    lens = [1500, 2049, 3000, 4100, 5000, 5120]
+    idx = [np.sort(g.choice(n, L, replace=False)).astype(np.int32) for L in lens]
+    val = [(1 + g.geometric(0.6, L) - 1).astype(np.float32) for L in lens]
+    ptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    idx, val = np.concatenate(idx), np.concatenate(val)
+    m = P.nmfkl_model_create(torch.from_numpy(W).cuda())
+    F, passes, kl = P.nmfkl_foldin(m, *device_docs(ptr, idx, val))
+    Fg, pg, kg = F.cpu().numpy(), passes.cpu().numpy(), kl.cpu().numpy()
+    P.nmfkl_model_destroy(m)
+    Fo, po, ko, _ = oracle.foldin(W, ptr, idx, val)
+    same = pg == po
+    print(f"long docs: passes gpu {pg.tolist()} oracle {po.tolist()}; F rel {relf(Fg[same], Fo[same]):.2e}; "
+          f"KL rel max {np.max(np.abs(kg - ko) / ko):.2e}")
+    assert np.all(np.abs(pg - po) <= 1) and same.sum() >= len(lens) - 1
+    assert relf(Fg[same], Fo[same]) <= 1e-4
+    assert np.max(np.abs(kg - ko) / ko) <= 1e-5
+    too_long = np.arange(5121, dtype=np.int32)
+    srv = P.nmfkl_server_create(P.nmfkl_model_create(torch.from_numpy(W).cuda()), 1 << 20)
+    with pytest.raises(P.NmfklError) as ei:
+        P.nmfkl_server_submit(srv, 1, too_long, np.ones(too_long.size, np.float32))
+    assert ei.value.code == -6
