@@ -74,7 +74,9 @@ typedef struct nmfkl_params {
     int32_t collect_stats;     /* 1: count derivative evaluations / steps / guard events (slower) */
     int32_t collect_timings;   /* 1: bracket every launch group with HIP events (nmfkl_get_timings) */
     int32_t tuning;            /* implementation choices that do not change results; bit 0: batched
-                                  (lookahead) derivative sums also for segments of 257..1024 nonzeros */
+                                  (lookahead) derivative sums also for segments of 257..1024 nonzeros;
+                                  bit 1 (batches): blocks ordered problem by problem rather than by
+                                  segment length across problems */
     int32_t bin_shift;         /* mapping of segments of <= 1024 nonzeros to lanes (0..3, default 0):
                                   a segment of L nonzeros runs on the smallest lane group that holds
                                   L << bin_shift nonzeros (8, 16, 32, 64 or 256 lanes x 4).  Changes
@@ -234,7 +236,7 @@ int nmfkl_batch_run(nmfkl_batch* b, int32_t t0, int32_t nsweeps);
 int nmfkl_batch_objective(nmfkl_batch* b, double* D_out);
 
 /* Autotuner: times one outer iteration (iteration t) under each candidate mapping
- * (bin_shift 0..2, tuning bit 0 off/on) on the batch, restoring W, F and the model values after
+ * (bin_shift 0..2, tuning bits 0 and 1 off/on) on the batch, restoring W, F and the model values after
  * every trial, and keeps the fastest.  The factors are unchanged on return.  chosen (host,
  * may be NULL) receives the parameters now in use, with which nmfkl_create reproduces the
  * batch's results.  Synchronises. */

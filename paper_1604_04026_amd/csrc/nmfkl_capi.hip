@@ -70,8 +70,7 @@ struct nmfkl_handle {
     double* dscal = nullptr;      // device scalar (objective total)
     double* host_scal = nullptr;  // pinned host scalar
     unsigned long long* stats = nullptr;
-    double* coop_partials = nullptr;   // cross-block partial sums of long segments
-    unsigned* coop_counters = nullptr; // their arrival flags (one line per block)
+    unsigned long long* coop_words = nullptr;  // tagged cross-block partial sums of long segments
     unsigned* dev_err = nullptr;       // device-side error flags (bounded waits)
     int long_capacity = 0;             // co-resident long-segment blocks
     BinPlan binF, binW;
@@ -164,7 +163,7 @@ void release(nmfkl_handle* h) {
     f(h->csc2csr); f(h->csr2csc); f(h->obj_partials); f(h->sums2); f(h->dscal); f(h->stats);
     f(h->binF.work); f(h->binF.segs); f(h->binW.work); f(h->binW.segs);
     f(h->binF.long_work); f(h->binW.long_work);
-    f(h->coop_partials); f(h->coop_counters); f(h->dev_err); f(h->argtab); f(h->jobtab);
+    f(h->coop_words); f(h->dev_err); f(h->argtab); f(h->jobtab);
     if (h->host_scal) (void)hipHostFree(h->host_scal);
 }
 
@@ -191,8 +190,8 @@ void free_plan(BinPlan* p) {
 // problems are ordered by their first segment, longest first.  Longer segments: B =
 // ceil(L / kLongCapacity) blocks each; those with B = 1 in one ordinary launch, the others
 // packed longest first into cooperative rounds of at most long_capacity blocks.
-int plan_bins(const std::vector<SegSource>& src, int long_capacity, int bin_shift, BinPlan* plan,
-              std::string* err) {
+int plan_bins(const std::vector<SegSource>& src, int long_capacity, int bin_shift, bool problem_major,
+              BinPlan* plan, std::string* err) {
     struct LongSeg { int32_t q, prob; int64_t len; };
     const size_t ns = src.size();
     std::vector<std::vector<std::vector<int32_t>>> groups(kNumVariants, std::vector<std::vector<int32_t>>(ns));
@@ -218,9 +217,10 @@ int plan_bins(const std::vector<SegSource>& src, int long_capacity, int bin_shif
     }
     std::vector<int32_t> segs;
     std::vector<BlockWork> work;
+    struct Blk { int64_t key; size_t src, first; int count; int v; };
+    std::vector<Blk> all;
     for (int v = kNumVariants - 1; v >= 0; --v) {
         const int spb = kFusedThreads / kVariants[v].G;
-        struct Blk { int64_t key; size_t src, first; int count; };
         std::vector<Blk> blks;
         for (size_t i = 0; i < ns; ++i) {
             const std::vector<int64_t>& ptr = *src[i].ptr;
@@ -228,18 +228,23 @@ int plan_bins(const std::vector<SegSource>& src, int long_capacity, int bin_shif
             auto& g = groups[v][i];
             std::stable_sort(g.begin(), g.end(), [&](int32_t a, int32_t b) { return len(a) > len(b); });
             for (size_t k = 0; k < g.size(); k += spb)
-                blks.push_back(Blk{len(g[k]), i, k, (int)std::min<size_t>(spb, g.size() - k)});
+                blks.push_back(Blk{len(g[k]), i, k, (int)std::min<size_t>(spb, g.size() - k), v});
         }
         std::stable_sort(blks.begin(), blks.end(), [](const Blk& a, const Blk& b) { return a.key > b.key; });
-        for (const Blk& b : blks) {
-            BlockWork w;
-            w.variant = v;
-            w.first = (int32_t)segs.size();
-            w.count = b.count;
-            w.prob = src[b.src].prob;
-            for (int k = 0; k < b.count; ++k) segs.push_back(groups[v][b.src][b.first + k]);
-            work.push_back(w);
-        }
+        all.insert(all.end(), blks.begin(), blks.end());
+    }
+    // problem-major: the blocks of one problem together (variants longest first inside it), so
+    // that the launch works on few problems' fixed factors at a time (cache locality)
+    if (problem_major)
+        std::stable_sort(all.begin(), all.end(), [](const Blk& a, const Blk& b) { return a.src < b.src; });
+    for (const Blk& b : all) {
+        BlockWork w;
+        w.variant = b.v;
+        w.first = (int32_t)segs.size();
+        w.count = b.count;
+        w.prob = src[b.src].prob;
+        for (int k = 0; k < b.count; ++k) segs.push_back(groups[b.v][b.src][b.first + k]);
+        work.push_back(w);
     }
     auto dev_fail = [&](hipError_t e, const char* what) {
         *err = std::string(what) + ": " + hipGetErrorString(e);
@@ -258,8 +263,14 @@ int plan_bins(const std::vector<SegSource>& src, int long_capacity, int bin_shif
 
     std::stable_sort(longs.begin(), longs.end(), [](const LongSeg& a, const LongSeg& b) { return a.len > b.len; });
     std::vector<LongWork> lw;
-    for (const LongSeg& l : longs)
-        if (l.len <= kLongCapacity) lw.push_back(LongWork{l.q, 0, 1, 0, l.prob, 0});
+    {
+        std::vector<LongSeg> single;
+        for (const LongSeg& l : longs)
+            if (l.len <= kLongCapacity) single.push_back(l);
+        if (problem_major)
+            std::stable_sort(single.begin(), single.end(), [](const LongSeg& a, const LongSeg& b) { return a.prob < b.prob; });
+        for (const LongSeg& l : single) lw.push_back(LongWork{l.q, 0, 1, 0, l.prob, 0});
+    }
     plan->single_blocks = (int)lw.size();
     BinPlan::Round cur{(int)lw.size(), 0, 0, 0};
     for (const LongSeg& l : longs) {
@@ -394,7 +405,7 @@ int refresh_model(nmfkl_handle* h) {
 
 // Enqueues one half-sweep's sweep launches (long single-block, cooperative rounds, fused)
 // over the plan, with the argument table tab; timed: bracket them with the handle's timers.
-hipError_t enqueue_plan(const BinPlan& plan, const SweepArgs* tab, double* coop_partials, unsigned* coop_flags,
+hipError_t enqueue_plan(const BinPlan& plan, const SweepArgs* tab, unsigned long long* coop_words,
                         unsigned* dev_err, bool cooperative, bool lookahead, hipStream_t s,
                         nmfkl_handle* timed, int long_kind, int fused_kind) {
     hipError_t e;
@@ -402,8 +413,8 @@ hipError_t enqueue_plan(const BinPlan& plan, const SweepArgs* tab, double* coop_
     const int tl = (timed && any_long) ? timer_begin(timed, long_kind) : -1;
     if ((e = launch_sweep_long_single(tab, plan.long_work, plan.single_blocks, s)) != hipSuccess) return e;
     for (const auto& rd : plan.rounds)
-        if ((e = launch_sweep_long(tab, plan.long_work + rd.first, rd.nblocks, coop_partials, coop_flags,
-                                   rd.ngroups, dev_err, rd.pmax, cooperative, s)) != hipSuccess)
+        if ((e = launch_sweep_long(tab, plan.long_work + rd.first, rd.nblocks, coop_words, rd.ngroups, dev_err,
+                                   rd.pmax, cooperative, s)) != hipSuccess)
             return e;
     if (timed) timer_end(timed, tl);
     const int tf = (timed && plan.nblocks) ? timer_begin(timed, fused_kind) : -1;
@@ -435,7 +446,7 @@ int half_sweep(nmfkl_handle* h, int32_t t, bool fhalf) {
     int ai;
     if (fhalf) ai = (h->model == kModelCsc || h->model == kModelCscFresh) ? kArgFfromCsc : kArgFfromCsr;
     else ai = h->model == kModelCsr ? kArgWfromCsr : kArgWfromCsc;
-    HIP_TRY(h, enqueue_plan(plan, h->argtab + ai, h->coop_partials, h->coop_counters, h->dev_err, true,
+    HIP_TRY(h, enqueue_plan(plan, h->argtab + ai, h->coop_words, h->dev_err, true,
                             (h->prm.tuning & 1) != 0, h->stream, h,
                             fhalf ? NMFKL_T_LONG_F : NMFKL_T_LONG_W, fhalf ? NMFKL_T_FUSED_F : NMFKL_T_FUSED_W));
     h->model = fhalf ? kModelCsc : kModelCsr;
@@ -583,18 +594,19 @@ int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_str
         CREATE_HIP(hipMemcpy(h->hptr_csc.data(), pr.csc_ptr, h->hptr_csc.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
         CREATE_HIP(hipMemcpy(h->hptr_csr.data(), pr.csr_ptr, h->hptr_csr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
         std::string why_plan;
-        int rc = plan_bins({SegSource{&h->hptr_csc, pr.r, 0}}, h->long_capacity, prm.bin_shift, &h->binF, &why_plan);
-        if (!rc) rc = plan_bins({SegSource{&h->hptr_csr, pr.r, 0}}, h->long_capacity, prm.bin_shift, &h->binW, &why_plan);
+        int rc = plan_bins({SegSource{&h->hptr_csc, pr.r, 0}}, h->long_capacity, prm.bin_shift, false, &h->binF,
+                           &why_plan);
+        if (!rc)
+            rc = plan_bins({SegSource{&h->hptr_csr, pr.r, 0}}, h->long_capacity, prm.bin_shift, false, &h->binW,
+                           &why_plan);
         if (rc) {
             fail(h, rc, why_plan);
             return bail(rc);
         }
         const int groups = std::max(h->binF.max_groups, h->binW.max_groups);
         const int pmax = std::max(h->binF.max_pmax, h->binW.max_pmax);
-        // k_sweep_long<true> addresses partials + group * (2 * pmax * kCoopValues) + ...
-        CREATE_HIP(dalloc(&h->coop_partials, (size_t)std::max(groups, 1) * 2 * std::max(pmax, 1) * kCoopValues));
-        // ... and flags + group * (pmax * kFlagStride) + part * kFlagStride
-        CREATE_HIP(dalloc(&h->coop_counters, (size_t)std::max(groups, 1) * std::max(pmax, 1) * kFlagStride));
+        // k_sweep_long<true> addresses words + group * (2 * pmax * kCoopValues) + ...
+        CREATE_HIP(dalloc(&h->coop_words, (size_t)std::max(groups, 1) * 2 * std::max(pmax, 1) * kCoopValues));
         CREATE_HIP(dalloc(&h->dev_err, 1));
         CREATE_HIP(hipMemsetAsync(h->dev_err, 0, sizeof(unsigned), h->stream));
     }
@@ -744,9 +756,8 @@ struct nmfkl_batch {
     int perm_blocks[2] = {0, 0};
     int nsum[2] = {0, 0};
     BinPlan plan[2];
-    double* coop_partials = nullptr;
-    unsigned* coop_flags = nullptr;
-    size_t coop_partials_n = 0, coop_flags_n = 0;
+    unsigned long long* coop_words = nullptr;
+    size_t coop_words_n = 0;
     unsigned* dev_err = nullptr;
     int64_t* t_dev = nullptr;
     int long_capacity = 0;
@@ -781,8 +792,8 @@ void batch_release(nmfkl_batch* b) {
     free_plan(&b->plan[0]);
     free_plan(&b->plan[1]);
     auto f = [](void* p) { if (p) (void)hipFree(p); };
-    f(b->argtab); f(b->jobtab); f(b->coop_partials); f(b->coop_flags); f(b->dev_err); f(b->t_dev);
-    b->argtab = nullptr; b->jobtab = nullptr; b->coop_partials = nullptr; b->coop_flags = nullptr;
+    f(b->argtab); f(b->jobtab); f(b->coop_words); f(b->dev_err); f(b->t_dev);
+    b->argtab = nullptr; b->jobtab = nullptr; b->coop_words = nullptr;
     b->dev_err = nullptr; b->t_dev = nullptr;
     if (b->cap) (void)hipStreamDestroy(b->cap);
     b->cap = nullptr;
@@ -802,23 +813,18 @@ int batch_plan(nmfkl_batch* b) {
         srcW.push_back(SegSource{&b->hs[p]->hptr_csr, b->hs[p]->prob.r, (int)p});
     }
     std::string why;
-    int rc = plan_bins(srcF, b->long_capacity, b->prm.bin_shift, &b->plan[0], &why);
-    if (!rc) rc = plan_bins(srcW, b->long_capacity, b->prm.bin_shift, &b->plan[1], &why);
+    const bool pm = (b->prm.tuning & 2) != 0;
+    int rc = plan_bins(srcF, b->long_capacity, b->prm.bin_shift, pm, &b->plan[0], &why);
+    if (!rc) rc = plan_bins(srcW, b->long_capacity, b->prm.bin_shift, pm, &b->plan[1], &why);
     if (rc) return bfail(b, rc, why);
     const int groups = std::max(std::max(b->plan[0].max_groups, b->plan[1].max_groups), 1);
     const int pmax = std::max(std::max(b->plan[0].max_pmax, b->plan[1].max_pmax), 1);
-    const size_t np = (size_t)groups * 2 * pmax * kCoopValues, nf = (size_t)groups * pmax * kFlagStride;
-    if (np > b->coop_partials_n) {
-        if (b->coop_partials) (void)hipFree(b->coop_partials);
-        b->coop_partials = nullptr;
-        BHIP(b, dalloc(&b->coop_partials, np));
-        b->coop_partials_n = np;
-    }
-    if (nf > b->coop_flags_n) {
-        if (b->coop_flags) (void)hipFree(b->coop_flags);
-        b->coop_flags = nullptr;
-        BHIP(b, dalloc(&b->coop_flags, nf));
-        b->coop_flags_n = nf;
+    const size_t nw = (size_t)groups * 2 * pmax * kCoopValues;
+    if (nw > b->coop_words_n) {
+        if (b->coop_words) (void)hipFree(b->coop_words);
+        b->coop_words = nullptr;
+        BHIP(b, dalloc(&b->coop_words, nw));
+        b->coop_words_n = nw;
     }
     return NMFKL_OK;
 }
@@ -849,7 +855,7 @@ hipError_t batch_enqueue(nmfkl_batch* b, hipStream_t s, int nsweeps, bool cooper
             const PermJob* jobs = b->jobtab + (size_t)half * np;
             if ((e = launch_permute_jobs(jobs, np, b->perm_blocks[half], k, b->t_dev, s)) != hipSuccess) return e;
             if ((e = launch_finalize_jobs(jobs, np, b->nsum[half], s)) != hipSuccess) return e;
-            if ((e = enqueue_plan(b->plan[half], b->argtab + (size_t)half * np, b->coop_partials, b->coop_flags,
+            if ((e = enqueue_plan(b->plan[half], b->argtab + (size_t)half * np, b->coop_words,
                                   b->dev_err, cooperative, la, s, nullptr, 0, 0)) != hipSuccess)
                 return e;
         }
@@ -1054,9 +1060,9 @@ int nmfkl_batch_tune(nmfkl_batch* b, int32_t t, nmfkl_params* chosen) {
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e == hipSuccess) e = copy_all(true);
     for (int shift = 0; shift <= 2 && e == hipSuccess && rc == NMFKL_OK; ++shift)
-        for (int la = 0; la <= 1 && e == hipSuccess && rc == NMFKL_OK; ++la) {
+        for (int bits = 0; bits <= 3 && e == hipSuccess && rc == NMFKL_OK; ++bits) {
             b->prm.bin_shift = shift;
-            b->prm.tuning = (orig.tuning & ~1) | la;
+            b->prm.tuning = (orig.tuning & ~3) | bits;
             rc = batch_plan(b);
             if (rc) break;
             float ms = 0.0f;

@@ -172,19 +172,15 @@ hipError_t launch_sweep_fused(const SweepArgs* tab, const BlockWork* work, const
 // Long segments that fit one block (B = 1): ordinary launch.
 hipError_t launch_sweep_long_single(const SweepArgs* tab, const LongWork* work, int nblocks,
                                     hipStream_t stream);
-// Partial sums a cooperating block publishes per reduction (S1 and S2 of every chunk
-// coordinate).
+// Partial sums a cooperating block publishes per reduction (at most S1 and S2 of every
+// coordinate of an 8-wide chunk), one tagged 64-bit word each.
 constexpr int kCoopValues = 2 * kChunk;
-// Words per arrival flag of a cooperating block (one 128-byte line each).
-constexpr int kFlagStride = 32;
-// Cooperative launch over long segments; zeroes the arrival flags first.  partials holds
-// 2 * pmax * kCoopValues doubles and flags pmax * kFlagStride words per group (pmax =
-// largest B in the launch).
+// Cooperative launch over long segments; zeroes the group's tagged partial words first
+// (2 * pmax * kCoopValues words per group, pmax = largest B in the launch).
 // cooperative = false: ordinary launch of the same grid (inside a captured graph), which
 // relies on the grid fitting the device's co-resident capacity; the waits stay bounded.
-hipError_t launch_sweep_long(const SweepArgs* tab, const LongWork* work, int nblocks, double* partials,
-                             unsigned* flags, int ngroups, unsigned* err, int pmax, bool cooperative,
-                             hipStream_t stream);
+hipError_t launch_sweep_long(const SweepArgs* tab, const LongWork* work, int nblocks, unsigned long long* words,
+                             int ngroups, unsigned* err, int pmax, bool cooperative, hipStream_t stream);
 // Co-resident blocks of the long-segment kernel per compute unit (0 on failure).
 int long_kernel_blocks_per_cu();
 hipError_t launch_model_objective(const int64_t* csc_ptr, const int32_t* csc_idx,

@@ -180,25 +180,46 @@ hipError_t launch_finalize_jobs(const PermJob* jobs, int njobs, int nsum, hipStr
 template <int E>
 struct RegElems {
     static constexpr int kE = E;
+    static constexpr bool kStoresWU = true;
     double ax[E];
     int32_t id_[E];
     float v_[E], w_[E], u_[E];
     __device__ __forceinline__ int32_t& id(int e) { return id_[e]; }
     __device__ __forceinline__ float& v(int e) { return v_[e]; }
-    __device__ __forceinline__ float& w(int e) { return w_[e]; }
-    __device__ __forceinline__ float& u(int e) { return u_[e]; }
+    __device__ __forceinline__ void wu(int e, float eps, float& w, float& u) { w = w_[e]; u = u_[e]; }
+    __device__ __forceinline__ void set_wu(int e, float w, float u) { w_[e] = w; u_[e] = u; }
 };
 
 template <int E, int STRIDE>
 struct LdsElems {
     static constexpr int kE = E;
+    static constexpr bool kStoresWU = true;
     double ax[E];
     int32_t* idp;
     float *vp, *wp, *up;
     __device__ __forceinline__ int32_t& id(int e) { return idp[e * STRIDE]; }
     __device__ __forceinline__ float& v(int e) { return vp[e * STRIDE]; }
-    __device__ __forceinline__ float& w(int e) { return wp[e * STRIDE]; }
-    __device__ __forceinline__ float& u(int e) { return up[e * STRIDE]; }
+    __device__ __forceinline__ void wu(int e, float eps, float& w, float& u) { w = wp[e * STRIDE]; u = up[e * STRIDE]; }
+    __device__ __forceinline__ void set_wu(int e, float w, float u) { wp[e * STRIDE] = w; up[e * STRIDE] = u; }
+};
+
+// Counts and ids in LDS, the model in registers; w and u are recomputed from the model when
+// needed (by the same formula that produces them on the other paths, so the values agree).
+template <int E, int STRIDE>
+struct LdsElemsNoWU {
+    static constexpr int kE = E;
+    static constexpr bool kStoresWU = false;
+    double ax[E];
+    int32_t* idp;
+    float* vp;
+    __device__ __forceinline__ int32_t& id(int e) { return idp[e * STRIDE]; }
+    __device__ __forceinline__ float& v(int e) { return vp[e * STRIDE]; }
+    __device__ __forceinline__ void wu(int e, float eps, float& w, float& u) {
+        const float ri = __builtin_amdgcn_rcpf((float)ax[e] + eps);
+        w = vp[e * STRIDE] * ri;
+        u = w * ri;
+    }
+    __device__ __forceinline__ void set_wu(int, float, float) {}
 };
 
 // ---- segment-wide all-reduce of NV partial sums ----------------------------------------
@@ -282,110 +303,112 @@ struct BlockReducer {
 };
 
 // A long segment split over B co-resident blocks (cooperative launch).  Each reduction:
-// block sum; lanes i < NV publish partial i (float64) into slot `round & 1` of the group's
-// partials with coherent atomic stores; once they are performed, thread 0 stores the
-// block's round number in its own flag line.  Wave 0 then polls the B flags in parallel (no
-// shared counter: same-address atomics from many blocks serialise at the coherence point)
-// until every block has published this round.  All threads read the partials, thread
-// (i, j) adding partial i of blocks j, j+16, ..., and thread i < NV adds the 16 results in
-// order, so every block obtains the same totals.  Every shared access is an atomic
-// performed at the device coherence point, so no cache-maintaining fence is needed.  The
-// wait is bounded: after kSpinLimit polls, or once any block has recorded an error, the
-// block records an error and continues (the host reports it at the next synchronising call).
+// block sum (float32, exactly representable in float64); lanes i < NV publish partial i as
+// one 64-bit word (round tag << 32 | float bits) into slot `round & 1` of the group's
+// partials with a coherent atomic store.  Readers poll the data words themselves: thread
+// (i, j) loads word i of blocks j, j+16, ... (up to kInFlight loads in flight) until every
+// tag equals this round's, adding the values in float64 in block order; thread i < NV then
+// adds the 16 results in order, so every block obtains the same totals.  One round trip per
+// exchange: no separate arrival flag and no wait for the stores to be performed.  The
+// slot of round k is rewritten at round k + 2 only after every block has published round
+// k + 1, which each does after reading round k.  Every shared access is an atomic performed
+// at the device coherence point.  The waits are bounded: after kSpinLimit polls, or once any
+// block has recorded an error, the block records an error and continues (the host reports it
+// at the next synchronising call).  The words are zeroed before each launch.
 constexpr unsigned kSpinLimit = 1u << 20;
 
 template <int NT>
 struct CoopReducer {
-    static_assert(NT == 16 * kMaxRed, "the partial read uses NT / kMaxRed lanes per value");
+    static constexpr int J = NT / kMaxRed;   // block groups per value
+    static constexpr int kInFlight = 4;
     BlockReducer<NT> blk;
-    double* tmp;        // LDS, 16 * kMaxRed doubles
-    double* bcast;      // LDS, kMaxRed doubles
-    double* partials;   // global: [2][B][kMaxRed] for this group
-    unsigned* flags;    // global: B flag lines of kFlagStride words for this group
-    unsigned* err;      // global error flags
+    double* tmp;                 // LDS, J * kMaxRed doubles
+    double* bcast;               // LDS, kMaxRed doubles
+    unsigned long long* words;   // global: [2][B][kMaxRed] tagged partials of this group
+    unsigned* err;               // global error flags
     int B, part;
     unsigned round;
     template <int NV>
     __device__ __forceinline__ void sum(float (&v)[NV], int lo) {
+        static_assert(NV <= kMaxRed, "at most kMaxRed values per exchange");
         blk.sum(v, lo);
         if (B == 1) return;
-        const unsigned slot = round & 1u;
+        const unsigned tag = round + 1u;
+        unsigned long long* slot = words + (size_t)(round & 1u) * B * kMaxRed;
         const int tid = threadIdx.x;
         if (tid >= lo && tid < NV) {
             float mine = 0.0f;
 #pragma unroll
             for (int i = 0; i < NV; ++i)
                 if (i == tid) mine = v[i];
-            unsigned long long* p = reinterpret_cast<unsigned long long*>(partials) +
-                                    ((size_t)slot * B + part) * kMaxRed + tid;
-            __hip_atomic_store(p, (unsigned long long)__double_as_longlong((double)mine),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(slot + (size_t)part * kMaxRed + tid,
+                               ((unsigned long long)tag << 32) | __float_as_uint(mine), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         }
-        if (tid < 64) {
-            // the partial stores of this wave have been performed before the flag is raised
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-            if (tid == 0)
-                __hip_atomic_store(flags + (size_t)part * kFlagStride, round + 1u, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            unsigned spins = 0;
-            for (;;) {
-                bool ok = true;
-                for (int b = tid; b < B; b += 64)
-                    ok &= __hip_atomic_load(flags + (size_t)b * kFlagStride, __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT) >= round + 1u;
-                if (__all(ok)) break;
-                __builtin_amdgcn_s_sleep(1);
-                if (++spins > kSpinLimit ||
-                    __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                    if (tid == 0) atomicOr(err, 1u);
-                    break;
+        const int i = tid % kMaxRed, j = tid / kMaxRed;
+        double acc = 0.0;
+        if (i >= lo && i < NV) {
+            for (int b0 = j; b0 < B; b0 += J * kInFlight) {
+                unsigned long long w[kInFlight];
+                unsigned spins = 0;
+                for (;;) {
+                    bool ok = true;
+#pragma unroll
+                    for (int q = 0; q < kInFlight; ++q) {
+                        const int b = b0 + q * J;
+                        w[q] = b < B ? __hip_atomic_load(slot + (size_t)b * kMaxRed + i, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT)
+                                     : ((unsigned long long)tag << 32);
+                        ok &= (unsigned)(w[q] >> 32) == tag;
+                    }
+                    if (ok) break;
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++spins > kSpinLimit ||
+                        __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                        atomicOr(err, 1u);
+                        break;
+                    }
                 }
+#pragma unroll
+                for (int q = 0; q < kInFlight; ++q)
+                    acc += (double)__uint_as_float((unsigned)(w[q] & 0xFFFFFFFFull));
             }
         }
-        __syncthreads();
-        {
-            const int i = tid % kMaxRed, j = tid / kMaxRed;
-            double acc = 0.0;
-            if (i >= lo && i < NV) {
-                const double* q = partials + (size_t)slot * B * kMaxRed + i;
-                for (int b = j; b < B; b += NT / kMaxRed)
-                    acc += __hip_atomic_load(q + (size_t)b * kMaxRed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            tmp[j * kMaxRed + i] = acc;
-        }
+        tmp[j * kMaxRed + i] = acc;
         __syncthreads();
         if (tid >= lo && tid < NV) {
-            double acc = 0.0;
-            for (int j = 0; j < NT / kMaxRed; ++j) acc += tmp[j * kMaxRed + tid];
-            bcast[tid] = acc;
+            double t = 0.0;
+            for (int q = 0; q < J; ++q) t += tmp[q * kMaxRed + tid];
+            bcast[tid] = t;
         }
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < NV; ++i)
-            if (i >= lo) v[i] = (float)bcast[i];
+        for (int q = 0; q < NV; ++q)
+            if (q >= lo) v[q] = (float)bcast[q];
         ++round;
     }
 };
 
 // Elements handled by this lane: l = lo + lane + STRIDE * e, e < E, restricted to l < L.
-template <int E, int STRIDE, class St>
+// A tile chunk holds CW consecutive permuted coordinates (CW / 4 float4 per nonzero).
+template <int E, int STRIDE, int CW, class St>
 __device__ __forceinline__ void load_chunk(const SweepArgs& a, St& st, int L, int lo,
-                                           int lane, int c, float4 (&t)[E][2]) {
+                                           int lane, int c, float4 (&t)[E][CW / 4]) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         if (lo + lane + STRIDE * e < L) {
-            const float4* p = reinterpret_cast<const float4*>(a.Ap + (int64_t)st.id(e) * a.Sp + c * kChunk);
-            t[e][0] = p[0];
-            t[e][1] = p[1];
+            const float4* p = reinterpret_cast<const float4*>(a.Ap + (int64_t)st.id(e) * a.Sp + c * CW);
+#pragma unroll
+            for (int q = 0; q < CW / 4; ++q) t[e][q] = p[q];
         } else {
-            t[e][0] = make_float4(0.f, 0.f, 0.f, 0.f);
-            t[e][1] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int q = 0; q < CW / 4; ++q) t[e][q] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
     }
 }
 
-template <int E>
-__device__ __forceinline__ float comp(const float4 (&t)[E][2], int e, int cc) {
+template <int E, int CW>
+__device__ __forceinline__ float comp(const float4 (&t)[E][CW / 4], int e, int cc) {
     const float4 q = t[e][cc >> 2];
     switch (cc & 3) {
         case 0: return q.x;
@@ -395,22 +418,22 @@ __device__ __forceinline__ float comp(const float4 (&t)[E][2], int e, int cc) {
     }
 }
 
-// Alg. 2's inner loop for coordinate s = c*kChunk + cc of one segment.  t holds the chunk's
+// Alg. 2's inner loop for coordinate s = c*CW + cc of one segment.  t holds the chunk's
 // fixed-factor values for the lane's nonzeros, xs the segment's x in LDS (permuted order).
 // LA (lookahead): LS[2k], LS[2k+1] hold eq. 6's sums S1, S2 of chunk coordinate k >= cc at
 // the current model; every trial evaluation also computes the sums of the chunk
 // coordinates after cc at the trial model, so that an accepted step leaves LS valid.  The
 // sums are the same numbers the sequential order would compute later from the same model.
 // Without LA, the coordinate's own sums are evaluated here.
-template <int cc, int E, bool LA, class Red, class St>
+template <int cc, int E, bool LA, int CW, class Red, class St>
 __device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s,
-                                                const float4 (&t)[E][2], St& st, float* xs,
-                                                Red& red, float (&LS)[kMaxRed], unsigned (&cnt)[6]) {
+                                                const float4 (&t)[E][CW / 4], St& st, float* xs,
+                                                Red& red, float (&LS)[2 * CW], unsigned (&cnt)[6]) {
     float xk = xs[s];
     const double sA = a.sumA[s];
     float tk[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) tk[e] = comp<E>(t, e, cc);
+    for (int e = 0; e < E; ++e) tk[e] = comp<E, CW>(t, e, cc);
     float S1, S2;
     if constexpr (LA) {
         S1 = LS[2 * cc];
@@ -419,8 +442,10 @@ __device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s,
         float acc[2] = {0.0f, 0.0f};
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            acc[0] = fmaf(tk[e], st.w(e), acc[0]);
-            acc[1] = fmaf(tk[e], tk[e] * st.u(e), acc[1]);
+            float we, ue;
+            st.wu(e, a.eps_log, we, ue);
+            acc[0] = fmaf(tk[e], we, acc[0]);
+            acc[1] = fmaf(tk[e], tk[e] * ue, acc[1]);
         }
         red.sum(acc, 0);
         S1 = acc[0];
@@ -444,14 +469,14 @@ __device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s,
         const float dN = d;  // Alg. 2's projected Newton step (the break test uses it)
         double mm[E];
         float wn[E], un[E];
-        float acc[kMaxRed];
+        float acc[2 * CW];
         double gn, Pn;
         float hn;
         int j = 0;
         bool rejected = false;
         for (;;) {
 #pragma unroll
-            for (int i = 0; i < kMaxRed; ++i) acc[i] = 0.0f;
+            for (int i = 0; i < 2 * CW; ++i) acc[i] = 0.0f;
             const double dd = (double)d;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
@@ -466,9 +491,9 @@ __device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s,
                 acc[2 * cc + 1] = fmaf(tk[e], tk[e] * uu, acc[2 * cc + 1]);
                 if constexpr (LA) {
 #pragma unroll
-                    for (int k = 0; k < kChunk; ++k) {
+                    for (int k = 0; k < CW; ++k) {
                         if (k > cc) {
-                            const float tq = comp<E>(t, e, k);
+                            const float tq = comp<E, CW>(t, e, k);
                             acc[2 * k] = fmaf(tq, ww, acc[2 * k]);
                             acc[2 * k + 1] = fmaf(tq, tq * uu, acc[2 * k + 1]);
                         }
@@ -498,12 +523,11 @@ __device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s,
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             st.ax[e] = mm[e];
-            st.w(e) = wn[e];
-            st.u(e) = un[e];
+            st.set_wu(e, wn[e], un[e]);
         }
         if constexpr (LA) {
 #pragma unroll
-            for (int k = 0; k < kChunk; ++k)
+            for (int k = 0; k < CW; ++k)
                 if (k > cc) {
                     LS[2 * k] = acc[2 * k];
                     LS[2 * k + 1] = acc[2 * k + 1];
@@ -527,25 +551,27 @@ __device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s,
 // compile-time constant, so every register array is indexed statically).
 // cmap (fold-in): x and sumA are kept in the original coordinate order and step s of the
 // pass visits coordinate cmap[s]; null: they are already in the sweep's order.
-template <int CC, int E, bool LA, class Red, class St>
-__device__ __forceinline__ void chunk_steps(const SweepArgs& a, int c, const float4 (&t)[E][2],
-                                            St& st, float* xs, Red& red, float (&LS)[kMaxRed],
+template <int CC, int E, bool LA, int CW, class Red, class St>
+__device__ __forceinline__ void chunk_steps(const SweepArgs& a, int c, const float4 (&t)[E][CW / 4],
+                                            St& st, float* xs, Red& red, float (&LS)[2 * CW],
                                             unsigned (&cnt)[6], const int32_t* cmap = nullptr) {
-    if constexpr (CC < kChunk) {
-        const int s = c * kChunk + CC;
+    if constexpr (CC < CW) {
+        const int s = c * CW + CC;
         if (s < a.r) {
-            coordinate_step<CC, E, LA>(a, cmap ? cmap[s] : s, t, st, xs, red, LS, cnt);
-            chunk_steps<CC + 1, E, LA>(a, c, t, st, xs, red, LS, cnt, cmap);
+            coordinate_step<CC, E, LA, CW>(a, cmap ? cmap[s] : s, t, st, xs, red, LS, cnt);
+            chunk_steps<CC + 1, E, LA, CW>(a, c, t, st, xs, red, LS, cnt, cmap);
         }
     }
 }
 
 // Alg. 2 on one segment (or on this block's part [lo, lo + STRIDE*E) of a long segment).
-// PREFETCH keeps the next tile chunk in flight while the current one is processed.
-template <int STRIDE, bool PREFETCH, bool LA, class Red, class St>
+// PREFETCH keeps the next tile chunk in flight while the current one is processed; CW is
+// the tile chunk width (coordinates per chunk).
+template <int STRIDE, bool PREFETCH, bool LA, int CW, class Red, class St>
 __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool active, int lane,
                                               int lo, bool count_stats, float* xs, Red& red, St& st) {
     constexpr int E = St::kE;
+    static_assert(LA || St::kStoresWU, "the per-coordinate evaluation reads stored w and u");
     int64_t base = 0;
     int L = 0;
     if (active) {
@@ -567,43 +593,43 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool 
         }
         const float ri = fast_rcp((float)st.ax[e] + a.eps_log);
         st.v(e) = v;
-        st.w(e) = v * ri;
-        st.u(e) = v * ri * ri;
+        st.set_wu(e, v * ri, v * ri * ri);
     }
     if (!active) return;
     unsigned cnt[6] = {0, 0, 0, 0, 0, 0};
-    const int nchunks = (a.r + kChunk - 1) / kChunk;
-    float4 cur[E][2];
-    load_chunk<E, STRIDE>(a, st, L, lo, lane, 0, cur);
+    const int nchunks = (a.r + CW - 1) / CW;
+    float4 cur[E][CW / 4];
+    load_chunk<E, STRIDE, CW>(a, st, L, lo, lane, 0, cur);
     for (int c = 0; c < nchunks; ++c) {
-        float4 nxt[E][2];
-        if (PREFETCH && c + 1 < nchunks) load_chunk<E, STRIDE>(a, st, L, lo, lane, c + 1, nxt);
-        float LS[kMaxRed];
+        float4 nxt[E][CW / 4];
+        if (PREFETCH && c + 1 < nchunks) load_chunk<E, STRIDE, CW>(a, st, L, lo, lane, c + 1, nxt);
+        float LS[2 * CW];
         if constexpr (LA) {
             // eq. 6's sums of every coordinate of the chunk at the current model
 #pragma unroll
-            for (int i = 0; i < kMaxRed; ++i) LS[i] = 0.0f;
+            for (int i = 0; i < 2 * CW; ++i) LS[i] = 0.0f;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
+                float we, ue;
+                st.wu(e, a.eps_log, we, ue);
 #pragma unroll
-                for (int k = 0; k < kChunk; ++k) {
-                    const float tq = comp<E>(cur, e, k);
-                    LS[2 * k] = fmaf(tq, st.w(e), LS[2 * k]);
-                    LS[2 * k + 1] = fmaf(tq, tq * st.u(e), LS[2 * k + 1]);
+                for (int k = 0; k < CW; ++k) {
+                    const float tq = comp<E, CW>(cur, e, k);
+                    LS[2 * k] = fmaf(tq, we, LS[2 * k]);
+                    LS[2 * k + 1] = fmaf(tq, tq * ue, LS[2 * k + 1]);
                 }
             }
             red.sum(LS, 0);
             cnt[1] += 1;
         }
-        chunk_steps<0, E, LA>(a, c, cur, st, xs, red, LS, cnt);
+        chunk_steps<0, E, LA, CW>(a, c, cur, st, xs, red, LS, cnt);
         if (PREFETCH) {
 #pragma unroll
-            for (int e = 0; e < E; ++e) {
-                cur[e][0] = nxt[e][0];
-                cur[e][1] = nxt[e][1];
-            }
+            for (int e = 0; e < E; ++e)
+#pragma unroll
+                for (int q = 0; q < CW / 4; ++q) cur[e][q] = nxt[e][q];
         } else if (c + 1 < nchunks) {
-            load_chunk<E, STRIDE>(a, st, L, lo, lane, c + 1, cur);
+            load_chunk<E, STRIDE, CW>(a, st, L, lo, lane, c + 1, cur);
         }
     }
     // write back the model at the nonzeros (this segment order)
@@ -617,6 +643,10 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool 
         for (int q = 0; q < 6; ++q) atomicAdd(&a.stats[q], (unsigned long long)cnt[q]);
     }
 }
+
+// Tile chunk width of the fused launch (8 coordinates: half the chunk loads of 4, whose
+// latency is exposed without prefetching).
+constexpr int kFusedCW = 8;
 
 template <int G, int E, bool LA>
 __device__ __forceinline__ void sweep_block(const SweepArgs& a, const BlockWork& wk, const int32_t* segs,
@@ -633,10 +663,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const BlockWork&
     RegElems<E> st;
     if constexpr (G <= 64) {
         WaveReducer<G> red;
-        sweep_segment<G, true, LA>(a, seg, active, lane, 0, true, xs, red, st);
+        sweep_segment<G, false, LA, kFusedCW>(a, seg, active, lane, 0, true, xs, red, st);
     } else {
         BlockReducer<G> red{red_lds, 0, nullptr};
-        sweep_segment<G, true, LA>(a, seg, active, lane, 0, true, xs, red, st);
+        sweep_segment<G, false, LA, kFusedCW>(a, seg, active, lane, 0, true, xs, red, st);
         __syncthreads();
     }
     if (active)
@@ -644,9 +674,11 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, const BlockWork&
 }
 
 // The fused binned launch: each block picks its (G, E) variant from the work table.
-// LA256 selects the lookahead form for the 256-lane variant.
+// LA256 selects the lookahead form for the 256-lane variant.  The kernel is latency-bound
+// (each coordinate is a dependent chain of sums, a reduction and Newton logic), so it runs
+// at 4 waves per SIMD (at most 128 registers) without a prefetched second tile chunk.
 template <bool LA256>
-__global__ void __launch_bounds__(kFusedThreads, 2)
+__global__ void __launch_bounds__(kFusedThreads, LA256 ? 2 : 4)
 k_sweep_fused(const SweepArgs* __restrict__ tab, const BlockWork* __restrict__ work,
               const int32_t* __restrict__ segs) {
     __shared__ float xs_all[(kFusedThreads / 8) * NMFKL_R_MAX];
@@ -676,26 +708,28 @@ hipError_t launch_sweep_fused(const SweepArgs* tab, const BlockWork* work, const
 // segment of L nonzeros takes B = ceil(L / kLongCapacity) blocks.  COOP = false: one block
 // per segment (B = 1), ordinary launch.  COOP = true: the blocks of a segment cooperate
 // through CoopReducer; all blocks of the launch are co-resident (cooperative launch), so
-// every wait ends.
+// every wait ends.  Counts and ids live in LDS, the model values in registers, w and u are
+// recomputed from the model at each chunk start, and tile chunks are 4 coordinates wide:
+// this keeps the kernel within 168 registers without spills, so 3 blocks share a compute
+// unit and a cooperative launch holds 1.5 times the nonzeros it would at 2.
+constexpr int kLongCW = 4;
+
 template <bool COOP>
-__global__ void __launch_bounds__(kLongThreads, 2)
+__global__ void __launch_bounds__(kLongThreads, 3)
 k_sweep_long(const SweepArgs* __restrict__ tab, const LongWork* __restrict__ work,
-             double* __restrict__ partials, unsigned* __restrict__ flags, unsigned* __restrict__ err,
-             int pmax) {
+             unsigned long long* __restrict__ words, unsigned* __restrict__ err, int pmax) {
     __shared__ float xs[NMFKL_R_MAX];
     __shared__ float red_lds[2 * (kLongThreads / 64) * kMaxRed];
-    __shared__ double tmp[(kLongThreads / kMaxRed) * kMaxRed];
+    __shared__ double tmp[CoopReducer<kLongThreads>::J * kMaxRed];
     __shared__ double bcast[kMaxRed];
     __shared__ int32_t s_id[kLongCapacity];
-    __shared__ float s_v[kLongCapacity], s_w[kLongCapacity], s_u[kLongCapacity];
+    __shared__ float s_v[kLongCapacity];
     const LongWork wk = work[blockIdx.x];
     const SweepArgs a = tab[wk.prob];
     const int lane = threadIdx.x;
-    LdsElems<kLongE, kLongThreads> st;
+    LdsElemsNoWU<kLongE, kLongThreads> st;
     st.idp = s_id + lane;
     st.vp = s_v + lane;
-    st.wp = s_w + lane;
-    st.up = s_u + lane;
     for (int s = lane; s < a.r; s += kLongThreads) xs[s] = a.X[(int64_t)wk.seg * a.r + a.ids[s]];
     __syncthreads();
     if constexpr (COOP) {
@@ -704,50 +738,48 @@ k_sweep_long(const SweepArgs* __restrict__ tab, const LongWork* __restrict__ wor
         red.blk.parity = 0;
         red.tmp = tmp;
         red.bcast = bcast;
-        red.partials = partials + (size_t)wk.group * 2 * pmax * kMaxRed;
-        red.flags = flags + (size_t)wk.group * pmax * kFlagStride;
+        red.words = words + (size_t)wk.group * 2 * pmax * kMaxRed;
         red.err = err;
         red.B = wk.B;
         red.part = wk.part;
         red.round = 0;
-        sweep_segment<kLongThreads, false, true>(a, wk.seg, true, lane, wk.part * kLongCapacity,
-                                                 wk.part == 0, xs, red, st);
+        sweep_segment<kLongThreads, false, true, kLongCW>(a, wk.seg, true, lane, wk.part * kLongCapacity,
+                                                          wk.part == 0, xs, red, st);
     } else {
         BlockReducer<kLongThreads> red{red_lds, 0, nullptr};
-        sweep_segment<kLongThreads, false, true>(a, wk.seg, true, lane, 0, true, xs, red, st);
+        sweep_segment<kLongThreads, false, true, kLongCW>(a, wk.seg, true, lane, 0, true, xs, red, st);
     }
     __syncthreads();
     if (wk.part == 0)
         for (int s = lane; s < a.r; s += kLongThreads) a.X[(int64_t)wk.seg * a.r + a.ids[s]] = xs[s];
 }
 
-__global__ void k_zero_u32(unsigned* p, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0u;
+__global__ void k_zero_u64(unsigned long long* p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
 }
 
 hipError_t launch_sweep_long_single(const SweepArgs* tab, const LongWork* work, int nblocks,
                                     hipStream_t stream) {
     if (nblocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_sweep_long<false>, dim3(nblocks), dim3(kLongThreads), 0, stream, tab, work,
-                       (double*)nullptr, (unsigned*)nullptr, (unsigned*)nullptr, 0);
+                       (unsigned long long*)nullptr, (unsigned*)nullptr, 0);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_long(const SweepArgs* tab, const LongWork* work, int nblocks, double* partials,
-                             unsigned* flags, int ngroups, unsigned* err, int pmax, bool cooperative,
-                             hipStream_t stream) {
+hipError_t launch_sweep_long(const SweepArgs* tab, const LongWork* work, int nblocks, unsigned long long* words,
+                             int ngroups, unsigned* err, int pmax, bool cooperative, hipStream_t stream) {
     if (nblocks <= 0) return hipSuccess;
-    const int nflags = ngroups * pmax * kFlagStride;
-    hipLaunchKernelGGL(k_zero_u32, dim3((nflags + 255) / 256), dim3(256), 0, stream, flags, nflags);
+    const int64_t nwords = (int64_t)ngroups * 2 * pmax * kCoopValues;
+    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((nwords + 255) / 256)), dim3(256), 0, stream, words, nwords);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (!cooperative) {
-        hipLaunchKernelGGL(k_sweep_long<true>, dim3(nblocks), dim3(kLongThreads), 0, stream, tab, work,
-                           partials, flags, err, pmax);
+        hipLaunchKernelGGL(k_sweep_long<true>, dim3(nblocks), dim3(kLongThreads), 0, stream, tab, work, words,
+                           err, pmax);
         return hipGetLastError();
     }
-    void* args[] = {&tab, &work, &partials, &flags, &err, &pmax};
+    void* args[] = {&tab, &work, &words, &err, &pmax};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_sweep_long<true>), dim3(nblocks),
                                       dim3(kLongThreads), args, 0, stream);
 }
@@ -830,8 +862,7 @@ __device__ __forceinline__ void foldin_segment(const FoldinArgs& f, const SweepA
     for (int e = 0; e < E; ++e) {
         st.ax[e] = (lane + G * e < L) ? x0 * f.rowsumW[st.id(e)] : 0.0;
         const float ri = fast_rcp((float)st.ax[e] + a.eps_log);
-        st.w(e) = st.v(e) * ri;
-        st.u(e) = st.v(e) * ri * ri;
+        st.set_wu(e, st.v(e) * ri, st.v(e) * ri * ri);
     }
     for (int k = lane; k < f.r; k += G) xs[k] = (float)x0;
     if constexpr (G > 64) __syncthreads();
@@ -846,23 +877,25 @@ __device__ __forceinline__ void foldin_segment(const FoldinArgs& f, const SweepA
         for (int c = 0; c < nchunks; ++c) {
             float4 cur[E][2];
             load_chunk_gather<E, G>(f, st, L, lane, c, perm_lds, cur);
-            float LS[kMaxRed];
+            float LS[2 * kChunk];
             if constexpr (LA) {
 #pragma unroll
-                for (int i = 0; i < kMaxRed; ++i) LS[i] = 0.0f;
+                for (int i = 0; i < 2 * kChunk; ++i) LS[i] = 0.0f;
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
+                    float we, ue;
+                    st.wu(e, a.eps_log, we, ue);
 #pragma unroll
                     for (int k = 0; k < kChunk; ++k) {
-                        const float tq = comp<E>(cur, e, k);
-                        LS[2 * k] = fmaf(tq, st.w(e), LS[2 * k]);
-                        LS[2 * k + 1] = fmaf(tq, tq * st.u(e), LS[2 * k + 1]);
+                        const float tq = comp<E, kChunk>(cur, e, k);
+                        LS[2 * k] = fmaf(tq, we, LS[2 * k]);
+                        LS[2 * k + 1] = fmaf(tq, tq * ue, LS[2 * k + 1]);
                     }
                 }
                 red.sum(LS, 0);
                 cnt[1] += 1;
             }
-            chunk_steps<0, E, LA>(a, c, cur, st, xs, red, LS, cnt, perm_lds);
+            chunk_steps<0, E, LA, kChunk>(a, c, cur, st, xs, red, LS, cnt, perm_lds);
         }
         if constexpr (G > 64) __syncthreads();
         ++p;
