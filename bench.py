@@ -41,8 +41,8 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1604_04026_amd", "csrc", "nmfkl_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_NAMES = {"fused_F": "k_sweep_fused", "fused_W": "k_sweep_fused", "long_F": "k_sweep_long",
-                "long_W": "k_sweep_long", "model": "k_model_terms", "sums_F": "k_permute_jobs",
-                "sums_W": "k_permute_jobs"}
+                "long_W": "k_sweep_long", "model": "k_model_objective", "terms": "k_model_terms",
+                "sums_F": "k_permute_jobs", "sums_W": "k_permute_jobs"}
 
 
 def source_hash() -> str:
@@ -259,7 +259,170 @@ def serving_leg(P, W, arrivals, ptr, idx, val, window_s, log):
     }
 
 
+COPY_BYTES = 256 << 20   # calibration copy of the traffic run
+
+
+def traffic_run(args):
+    """The command profiled for HBM traffic: a plain 256 MiB device copy (three times), then
+    warm-up and timed sweeps of the corpus.  Run under rocprofv3 --pmc FETCH_SIZE, then
+    under --pmc WRITE_SIZE; --traffic-summarize turns the two outputs into traffic.json."""
+    from paper_1604_04026_amd import workloads
+    prob = workloads.config(1, seed=args.seed)
+    import torch
+    import paper_1604_04026_amd as P
+    torch.cuda.set_device(0)
+    x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dev = P.upload(prob, "cuda:0")
+    h = P.nmfkl_create(dev, P.nmfkl_params_default(seed=args.seed, collect_timings=1))
+    for t in range(1 + args.steps):
+        P.nmfkl_sweep_F(h, t)
+        P.nmfkl_sweep_W(h, t)
+        P.nmfkl_objective_carried(h)
+    tim = P.nmfkl_get_timings(h)
+    P.nmfkl_destroy(h)
+    print(json.dumps({"sweeps": 1 + args.steps, "gather_bytes": {k: v["gather_bytes"] for k, v in tim.items()}}),
+          flush=True)
+
+
+def _counter_rows(path):
+    import csv
+    import glob
+    files = glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {path}")
+    with open(files[0]) as fh:
+        return list(csv.DictReader(fh))
+
+
+def traffic_summarize(fetch_dir, write_dir, out_path):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the traffic run -> bytes per launch of
+    each launch group, scaled by what the counters read for the calibration copy."""
+    def per_dispatch(rows, counter):
+        out = []
+        for r in rows:
+            if r.get("Counter_Name") != counter:
+                continue
+            out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], int(r.get("Grid_Size", 0) or 0),
+                        float(r["Counter_Value"])))
+        out.sort()
+        return out
+    res = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = per_dispatch(_counter_rows(d), counter)
+        copies = [v for _, name, _, v in rows if "copy" in name.lower() or "elementwise" in name.lower()]
+        copies = [v for v in copies if v > 0.25 * COPY_BYTES / 1024]
+        if not copies:
+            raise SystemExit(f"{counter}: calibration copy not found")
+        scale = (COPY_BYTES / 1024) / (sum(copies[1:] or copies) / len(copies[1:] or copies))
+        fused = [v for _, name, _, v in rows if "k_sweep_fused" in name]
+        model = [v for _, name, _, v in rows if "k_model_terms" in name]
+        # every sweep launches the F-half binned kernel, then the W-half one; skip the warm-up sweep
+        groups = {"fused_F": fused[2::2], "fused_W": fused[3::2], "terms": model[1:]}
+        res[counter] = {"scale": scale, "copy_kib": copies,
+                        "groups": {g: (sum(v) / len(v) * 1024 * scale if v else None) for g, v in groups.items()}}
+    groups = {}
+    for g in ("fused_F", "fused_W", "terms"):
+        f, w = res["FETCH_SIZE"]["groups"][g], res["WRITE_SIZE"]["groups"][g]
+        groups[g] = {"fetch_bytes_per_launch": f, "write_bytes_per_launch": w,
+                     "hbm_bytes_per_launch": (f + w) if f is not None and w is not None else None}
+    out = {"kernel_source_sha256_16": source_hash(),
+           "calibration": {"copy_bytes": COPY_BYTES, "fetch_scale": res["FETCH_SIZE"]["scale"],
+                           "write_scale": res["WRITE_SIZE"]["scale"]},
+           "groups": groups,
+           "commands": ["rocprofv3 --pmc FETCH_SIZE -d <fetch_dir> -o run --output-format csv -- "
+                        "python3 bench.py --traffic-run --steps 3",
+                        "rocprofv3 --pmc WRITE_SIZE -d <write_dir> -o run --output-format csv -- "
+                        "python3 bench.py --traffic-run --steps 3",
+                        "python3 bench.py --traffic-summarize <fetch_dir> <write_dir> profiles/traffic.json"]}
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def large_run(args, log):
+    """The large corpus (100,000 x 2,000,000, r = 100, ~300M nonzeros): sweeps with float32
+    tiles and with bfloat16-stored tiles from the same initial factors (objective and rate of
+    each, and their difference), and the first sweep's float32 F-half and W-half checked on
+    sampled columns and rows (the heaviest rows included) against the oracle."""
+    import numpy as np
+    from paper_1604_04026_amd import workloads
+    t0 = time.perf_counter()
+    prob = workloads.config(2, seed=args.seed, workers=args.workers,
+                            progress=lambda msg: print(f"[large] {msg} ({time.perf_counter() - t0:.0f} s)",
+                                                       file=sys.stderr, flush=True))
+    log(f"[large] generated n={prob.n} m={prob.m} r={prob.r} nnz={prob.nnz} ({time.perf_counter() - t0:.1f} s)")
+    import torch
+    import paper_1604_04026_amd as P
+    torch.cuda.set_device(0)
+    res = {}
+    first = None
+    for bf in (0, 1):
+        dev = P.upload(prob, "cuda:0")
+        h = P.nmfkl_create(dev, P.nmfkl_params_default(seed=args.seed, tile_bf16=bf, collect_timings=1))
+        P.nmfkl_sweep_F(h, 0)
+        if bf == 0:
+            Fg = dev.F.cpu().numpy()
+        P.nmfkl_sweep_W(h, 0)
+        if bf == 0:
+            first = (Fg, dev.W.cpu().numpy())
+        D1 = P.nmfkl_objective_carried(h)
+        P.nmfkl_reset_timings(h)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for t in range(1, 1 + args.steps):
+            P.nmfkl_sweep_F(h, t)
+            P.nmfkl_sweep_W(h, t)
+            P.nmfkl_objective_carried(h)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - ts
+        tim = P.nmfkl_get_timings(h)
+        D = P.nmfkl_objective(h)
+        P.nmfkl_destroy(h)
+        del dev
+        torch.cuda.empty_cache()
+        res[bf] = {"ms_per_sweep": el * 1e3 / args.steps, "updates_per_s": 2.0 * prob.nnz * prob.r * args.steps / el,
+                   "objective_after_first_sweep": D1, "objective": D, "sweeps": 1 + args.steps,
+                   "groups_ms": {k: round(v["ms_total"] / v["launches"], 4) for k, v in tim.items() if v["launches"]}}
+        log(f"[large] tile_bf16={bf}: {res[bf]}")
+    # sampled parity of the first sweep (float32 tiles) against the oracle
+    import oracle
+    Fg, Wg = first
+    ids = oracle.permutation(args.seed, 0, 0, prob.r)
+    W0, F0 = prob.W0.astype(np.float64), prob.F0.astype(np.float64)
+    rng = np.random.default_rng(7)
+    sumW = oracle.factor_sums(W0)
+    cols = rng.choice(prob.m, 500, replace=False)
+    Fo = np.array([oracle.alg2(prob.csc_idx[prob.csc_ptr[j]:prob.csc_ptr[j + 1]],
+                               prob.csc_val[prob.csc_ptr[j]:prob.csc_ptr[j + 1]], W0, sumW, F0[j], ids)[0]
+                   for j in cols])
+    F1 = Fg.astype(np.float64)
+    sumF = oracle.factor_sums(F1)
+    R = np.diff(prob.csr_ptr)
+    heavy = np.sort(np.argsort(R)[-6:])
+    rows = np.unique(np.concatenate([heavy, rng.choice(prob.n, 100, replace=False)]))
+    Wo = np.array([oracle.alg2(prob.csr_idx[prob.csr_ptr[i]:prob.csr_ptr[i + 1]],
+                               prob.csr_val[prob.csr_ptr[i]:prob.csr_ptr[i + 1]], F1, sumF, W0[i], ids)[0]
+                   for i in rows])
+    rel = lambda a, b: float(np.linalg.norm(a.astype(np.float64) - b) / np.linalg.norm(b))
+    out = {"workload": "large corpus 100000x2000000 r=100 (lognormal lengths median 92, cap 2000, Zipf(1.1) words, "
+                       "1+Geometric(0.6) counts)",
+           "n": prob.n, "m": prob.m, "r": prob.r, "nnz": prob.nnz, "longest_row": int(R.max()),
+           "float32_tiles": res[0], "bf16_tiles": res[1],
+           "bf16_objective_rel_diff": abs(res[1]["objective"] - res[0]["objective"]) / res[0]["objective"],
+           "sampled_parity_first_sweep": {"F_rel": rel(Fg[cols], Fo), "cols": int(cols.size),
+                                          "W_rel": rel(Wg[rows], Wo), "rows": int(rows.size),
+                                          "heaviest_rows": [int(R[i]) for i in heavy]}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
+    if len(sys.argv) >= 2 and sys.argv[1] == "--traffic-summarize":
+        traffic_summarize(sys.argv[2], sys.argv[3], sys.argv[4])
+        return
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -274,11 +437,21 @@ def main():
     ap.add_argument("--workers", type=int, default=16, help="processes generating the batched problems")
     ap.add_argument("--tuning", type=int, default=0, help="nmfkl_params.tuning bits (result-neutral)")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--traffic-run", action="store_true",
+                    help="the command profiled for HBM traffic (calibration copy + sweeps only)")
+    ap.add_argument("--large", action="store_true",
+                    help="the large corpus (100,000 x 2,000,000, r = 100): float32 vs bf16 tiles")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sweep's sharding over "
               "several GPUs is a design, not part of this build.", file=sys.stderr)
         sys.exit(2)
+    if args.traffic_run:
+        traffic_run(args)
+        return
+    if args.large:
+        large_run(args, (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True)))
+        return
 
     from paper_1604_04026_amd import workloads
 

@@ -82,6 +82,15 @@ typedef struct nmfkl_params {
                                   L << bin_shift nonzeros (8, 16, 32, 64 or 256 lanes x 4).  Changes
                                   the summation order of eq. 6's sums, hence results in the last
                                   bits; results are identical for identical bin_shift */
+    int32_t tile_bf16;         /* 0 (default): the fixed factor of a half-sweep is read in float32;
+                                  1: its permuted copy is stored in bfloat16 (round to nearest
+                                  even) and every half-sweep solves its subproblems for the rounded
+                                  factor: each column/row computes its model values from the rounded
+                                  tiles first (Alg. 2's first step), and the derivative sums, column
+                                  sums and model increments use the rounded values (arithmetic stays
+                                  float32 / float64).  Halves the bytes of each tile gather; results
+                                  differ from float32 tiles by the rounding (about 2^-9 relative per
+                                  factor entry) */
 } nmfkl_params;
 
 typedef struct nmfkl_problem {
@@ -113,8 +122,9 @@ typedef struct nmfkl_stats {
 #define NMFKL_T_SUMS_W 3   /* W-half: order, permuted copy of F and its column sums */
 #define NMFKL_T_FUSED_W 4  /* W-half: the binned launch over rows of <= 1024 nonzeros */
 #define NMFKL_T_LONG_W 5   /* W-half: cooperative launches over longer rows */
-#define NMFKL_T_MODEL 6    /* model values at the nonzeros (+ eq. 1 terms): refresh / objective */
-#define NMFKL_NUM_TIMED 7
+#define NMFKL_T_MODEL 6    /* model values at the nonzeros from W and F (+ eq. 1 terms) */
+#define NMFKL_T_TERMS 7    /* eq. 1 terms from the carried model values (nmfkl_objective_carried) */
+#define NMFKL_NUM_TIMED 8
 
 typedef struct nmfkl_kernel_timing {
     double ms_total;      /* summed HIP-event time of the timed launches */
@@ -122,7 +132,8 @@ typedef struct nmfkl_kernel_timing {
     double gather_bytes;  /* algorithmic bytes of one launch group under the gather model:
                              per nonzero 4 (index) + 4 (value) + 4r (the fixed factor's row),
                              per segment 8 (pointer) + 8r (x read and written); for the model
-                             pass per nonzero 4 + 4 + 4r + 8 (model written) + per column 4r */
+                             pass per nonzero 4 + 4 + 4r + 8 (model written) + per column 4r;
+                             for the carried terms per nonzero 8 (model) + 4 (value) */
     double updates;       /* coordinate updates of one launch group: nonzeros x r */
 } nmfkl_kernel_timing;
 

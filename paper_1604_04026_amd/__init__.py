@@ -56,7 +56,7 @@ class NmfklParams(ctypes.Structure):
         ("foldin_max_passes", ctypes.c_int32), ("foldin_tol", ctypes.c_double),
         ("refresh_model", ctypes.c_int32), ("collect_stats", ctypes.c_int32),
         ("collect_timings", ctypes.c_int32), ("tuning", ctypes.c_int32),
-        ("bin_shift", ctypes.c_int32),
+        ("bin_shift", ctypes.c_int32), ("tile_bf16", ctypes.c_int32),
     ]
 
 
@@ -78,7 +78,7 @@ class NmfklStats(ctypes.Structure):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
-TIMED = ["sums_F", "fused_F", "long_F", "sums_W", "fused_W", "long_W", "model"]
+TIMED = ["sums_F", "fused_F", "long_F", "sums_W", "fused_W", "long_W", "model", "terms"]
 
 
 class NmfklKernelTiming(ctypes.Structure):

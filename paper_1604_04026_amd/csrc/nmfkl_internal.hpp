@@ -82,6 +82,9 @@ struct PermJob {
     int32_t first_block, nblocks;
     int32_t first_sum;
     int32_t identity;     // 1: natural order, 0: the order of (seed, t, stream)
+    int32_t bf16;         // 1: the copy holds bfloat16 values (round to nearest even) and the
+                          //    column sums are those of the rounded values
+    int32_t pad;
 };
 
 // One half-sweep's per-launch arguments (kernels read them from a device table).
@@ -90,6 +93,7 @@ struct SweepArgs {
     const int32_t* idx;     // point ids of the nonzeros
     const float* val;       // values of the nonzeros
     const float* Ap;        // fixed factor, columns permuted into this sweep's order, row stride Sp
+                            // (float32, or bfloat16 when tile_bf16)
     const double* sumA;     // its column sums, permuted order
     const int32_t* ids;     // the order: permuted column s is original column ids[s]
     float* X;               // the factor being updated (point-major, row stride r)
@@ -101,6 +105,7 @@ struct SweepArgs {
     int32_t r;
     float alpha, beta, eps_log, eps_g, eps_x;
     int32_t t_max, j_max, literal_break, guard;
+    int32_t tile_bf16;      // 1: Ap holds bfloat16 values (row stride Sp elements)
 };
 
 // Fold-in launch arguments (the method parameters travel in a SweepArgs).
@@ -146,6 +151,10 @@ constexpr int kMaxFusedLength = 1024;   // 256 * 4
 constexpr int kLongThreads = 256;
 constexpr int kLongE = 8;
 constexpr int kLongCapacity = kLongThreads * kLongE;
+// Segments too long for the co-resident capacity at kLongCapacity per block: kHugeE nonzeros
+// per thread (fewer blocks per compute unit, twice the nonzeros per block).
+constexpr int kHugeE = 16;
+constexpr int kHugeCapacity = kLongThreads * kHugeE;
 
 // A block of a long-segment launch.
 struct LongWork {
@@ -179,10 +188,12 @@ constexpr int kCoopValues = 2 * kChunk;
 // (2 * pmax * kCoopValues words per group, pmax = largest B in the launch).
 // cooperative = false: ordinary launch of the same grid (inside a captured graph), which
 // relies on the grid fitting the device's co-resident capacity; the waits stay bounded.
+// huge: the kHugeE kernel (parts of kHugeCapacity nonzeros), else parts of kLongCapacity.
 hipError_t launch_sweep_long(const SweepArgs* tab, const LongWork* work, int nblocks, unsigned long long* words,
-                             int ngroups, unsigned* err, int pmax, bool cooperative, hipStream_t stream);
+                             int ngroups, unsigned* err, int pmax, bool huge, bool cooperative,
+                             hipStream_t stream);
 // Co-resident blocks of the long-segment kernel per compute unit (0 on failure).
-int long_kernel_blocks_per_cu();
+int long_kernel_blocks_per_cu(bool huge);
 hipError_t launch_model_objective(const int64_t* csc_ptr, const int32_t* csc_idx,
                                   const float* csc_val, int m, const float* W, const float* F, int r,
                                   double* Mcsc, double* partials, int nblocks, hipStream_t stream);

@@ -57,6 +57,14 @@ __device__ __forceinline__ float group_sum(float v) {
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // ------------------------------------------------- permuted copy + float64 column sums
+// bfloat16 of a finite float: round to nearest, ties to even (the upper 16 bits after adding
+// 0x7FFF plus the lowest kept bit).
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+    const unsigned u = __float_as_uint(x);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_to_float(uint16_t q) { return __uint_as_float((unsigned)q << 16); }
+
 // Job of a block: the last job whose first index is <= b (jobs in increasing order).
 template <class Key>
 __device__ __forceinline__ int find_job(const PermJob* jobs, int njobs, int b, Key key) {
@@ -127,8 +135,14 @@ __global__ void __launch_bounds__(256) k_permute_jobs(const PermJob* __restrict_
         double acc = 0.0;
         if (s < Sp) {
             for (int64_t p = p0 + ry; p < p1; p += 4) {
-                const float a = k >= 0 ? jb.A[p * r + k] : 0.0f;
-                if (jb.Ap) jb.Ap[p * Sp + s] = a;
+                float a = k >= 0 ? jb.A[p * r + k] : 0.0f;
+                if (jb.bf16) {
+                    const uint16_t q = bf16_rne(a);
+                    a = bf16_to_float(q);
+                    if (jb.Ap) reinterpret_cast<uint16_t*>(jb.Ap)[p * Sp + s] = q;
+                } else if (jb.Ap) {
+                    jb.Ap[p * Sp + s] = a;
+                }
                 acc += (double)a;
             }
         }
@@ -397,9 +411,28 @@ __device__ __forceinline__ void load_chunk(const SweepArgs& a, St& st, int L, in
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         if (lo + lane + STRIDE * e < L) {
-            const float4* p = reinterpret_cast<const float4*>(a.Ap + (int64_t)st.id(e) * a.Sp + c * CW);
+            if (a.tile_bf16) {
+                // CW bfloat16 values: CW / 8 16-byte loads (CW = 4: one 8-byte load)
+                const uint16_t* p = reinterpret_cast<const uint16_t*>(a.Ap) + (int64_t)st.id(e) * a.Sp + c * CW;
+                if constexpr (CW == 4) {
+                    const uint2 w = *reinterpret_cast<const uint2*>(p);
+                    t[e][0] = make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xFFFF0000u),
+                                          __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xFFFF0000u));
+                } else {
 #pragma unroll
-            for (int q = 0; q < CW / 4; ++q) t[e][q] = p[q];
+                    for (int q = 0; q < CW / 8; ++q) {
+                        const uint4 w = reinterpret_cast<const uint4*>(p)[q];
+                        t[e][2 * q] = make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xFFFF0000u),
+                                                  __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xFFFF0000u));
+                        t[e][2 * q + 1] = make_float4(__uint_as_float(w.z << 16), __uint_as_float(w.z & 0xFFFF0000u),
+                                                      __uint_as_float(w.w << 16), __uint_as_float(w.w & 0xFFFF0000u));
+                    }
+                }
+            } else {
+                const float4* p = reinterpret_cast<const float4*>(a.Ap + (int64_t)st.id(e) * a.Sp + c * CW);
+#pragma unroll
+                for (int q = 0; q < CW / 4; ++q) t[e][q] = p[q];
+            }
         } else {
 #pragma unroll
             for (int q = 0; q < CW / 4; ++q) t[e][q] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -586,19 +619,37 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool 
             const int64_t q = base + l;
             st.id(e) = a.idx[q];
             v = a.val[q];
-            st.ax[e] = a.Mmap ? a.Min[a.Mmap[q]] : a.Min[q];
+            st.ax[e] = a.tile_bf16 ? 0.0 : (a.Mmap ? a.Min[a.Mmap[q]] : a.Min[q]);
         } else {
             st.id(e) = 0;
             st.ax[e] = 0.0;
         }
-        const float ri = fast_rcp((float)st.ax[e] + a.eps_log);
         st.v(e) = v;
-        st.set_wu(e, v * ri, v * ri * ri);
     }
     if (!active) return;
-    unsigned cnt[6] = {0, 0, 0, 0, 0, 0};
     const int nchunks = (a.r + CW - 1) / CW;
     float4 cur[E][CW / 4];
+    if (a.tile_bf16) {
+        // Alg. 2's first step on the rounded factor: Ax at the segment's nonzeros from the
+        // tiles and x (float64 sums of exact float32 products), so that the model and the
+        // tiles define one subproblem
+        for (int c = 0; c < nchunks; ++c) {
+            load_chunk<E, STRIDE, CW>(a, st, L, lo, lane, c, cur);
+#pragma unroll
+            for (int cc = 0; cc < CW; ++cc) {
+                const int sc = c * CW + cc;
+                const double xv = sc < a.r ? (double)xs[sc] : 0.0;
+#pragma unroll
+                for (int e = 0; e < E; ++e) st.ax[e] = fma((double)comp<E, CW>(cur, e, cc), xv, st.ax[e]);
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const float ri = fast_rcp((float)st.ax[e] + a.eps_log);
+        st.set_wu(e, st.v(e) * ri, st.v(e) * ri * ri);
+    }
+    unsigned cnt[6] = {0, 0, 0, 0, 0, 0};
     load_chunk<E, STRIDE, CW>(a, st, L, lo, lane, 0, cur);
     for (int c = 0; c < nchunks; ++c) {
         float4 nxt[E][CW / 4];
@@ -714,20 +765,21 @@ hipError_t launch_sweep_fused(const SweepArgs* tab, const BlockWork* work, const
 // unit and a cooperative launch holds 1.5 times the nonzeros it would at 2.
 constexpr int kLongCW = 4;
 
-template <bool COOP>
-__global__ void __launch_bounds__(kLongThreads, 3)
+template <bool COOP, int E>
+__global__ void __launch_bounds__(kLongThreads, E <= kLongE ? 3 : 2)
 k_sweep_long(const SweepArgs* __restrict__ tab, const LongWork* __restrict__ work,
              unsigned long long* __restrict__ words, unsigned* __restrict__ err, int pmax) {
+    constexpr int CAP = kLongThreads * E;
     __shared__ float xs[NMFKL_R_MAX];
     __shared__ float red_lds[2 * (kLongThreads / 64) * kMaxRed];
     __shared__ double tmp[CoopReducer<kLongThreads>::J * kMaxRed];
     __shared__ double bcast[kMaxRed];
-    __shared__ int32_t s_id[kLongCapacity];
-    __shared__ float s_v[kLongCapacity];
+    __shared__ int32_t s_id[CAP];
+    __shared__ float s_v[CAP];
     const LongWork wk = work[blockIdx.x];
     const SweepArgs a = tab[wk.prob];
     const int lane = threadIdx.x;
-    LdsElemsNoWU<kLongE, kLongThreads> st;
+    LdsElemsNoWU<E, kLongThreads> st;
     st.idp = s_id + lane;
     st.vp = s_v + lane;
     for (int s = lane; s < a.r; s += kLongThreads) xs[s] = a.X[(int64_t)wk.seg * a.r + a.ids[s]];
@@ -743,7 +795,7 @@ k_sweep_long(const SweepArgs* __restrict__ tab, const LongWork* __restrict__ wor
         red.B = wk.B;
         red.part = wk.part;
         red.round = 0;
-        sweep_segment<kLongThreads, false, true, kLongCW>(a, wk.seg, true, lane, wk.part * kLongCapacity,
+        sweep_segment<kLongThreads, false, true, kLongCW>(a, wk.seg, true, lane, wk.part * CAP,
                                                           wk.part == 0, xs, red, st);
     } else {
         BlockReducer<kLongThreads> red{red_lds, 0, nullptr};
@@ -762,33 +814,39 @@ __global__ void k_zero_u64(unsigned long long* p, int64_t n) {
 hipError_t launch_sweep_long_single(const SweepArgs* tab, const LongWork* work, int nblocks,
                                     hipStream_t stream) {
     if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sweep_long<false>, dim3(nblocks), dim3(kLongThreads), 0, stream, tab, work,
+    hipLaunchKernelGGL((k_sweep_long<false, kLongE>), dim3(nblocks), dim3(kLongThreads), 0, stream, tab, work,
                        (unsigned long long*)nullptr, (unsigned*)nullptr, 0);
     return hipGetLastError();
 }
 
 hipError_t launch_sweep_long(const SweepArgs* tab, const LongWork* work, int nblocks, unsigned long long* words,
-                             int ngroups, unsigned* err, int pmax, bool cooperative, hipStream_t stream) {
+                             int ngroups, unsigned* err, int pmax, bool huge, bool cooperative,
+                             hipStream_t stream) {
     if (nblocks <= 0) return hipSuccess;
     const int64_t nwords = (int64_t)ngroups * 2 * pmax * kCoopValues;
     hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((nwords + 255) / 256)), dim3(256), 0, stream, words, nwords);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    const void* fn = huge ? reinterpret_cast<const void*>(k_sweep_long<true, kHugeE>)
+                          : reinterpret_cast<const void*>(k_sweep_long<true, kLongE>);
     if (!cooperative) {
-        hipLaunchKernelGGL(k_sweep_long<true>, dim3(nblocks), dim3(kLongThreads), 0, stream, tab, work, words,
-                           err, pmax);
+        if (huge)
+            hipLaunchKernelGGL((k_sweep_long<true, kHugeE>), dim3(nblocks), dim3(kLongThreads), 0, stream, tab,
+                               work, words, err, pmax);
+        else
+            hipLaunchKernelGGL((k_sweep_long<true, kLongE>), dim3(nblocks), dim3(kLongThreads), 0, stream, tab,
+                               work, words, err, pmax);
         return hipGetLastError();
     }
     void* args[] = {&tab, &work, &words, &err, &pmax};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_sweep_long<true>), dim3(nblocks),
-                                      dim3(kLongThreads), args, 0, stream);
+    return hipLaunchCooperativeKernel(fn, dim3(nblocks), dim3(kLongThreads), args, 0, stream);
 }
 
-int long_kernel_blocks_per_cu() {
+int long_kernel_blocks_per_cu(bool huge) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_sweep_long<true>),
-                                                     kLongThreads, 0) != hipSuccess)
-        return 0;
+    const void* fn = huge ? reinterpret_cast<const void*>(k_sweep_long<true, kHugeE>)
+                          : reinterpret_cast<const void*>(k_sweep_long<true, kLongE>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kLongThreads, 0) != hipSuccess) return 0;
     return nb;
 }
 

@@ -199,8 +199,18 @@ def _distinct_draws(lengths: np.ndarray, cdf: np.ndarray, g: np.random.Generator
     return np.concatenate(out_d), np.concatenate(out_r)
 
 
+def _corpus_block(args):
+    lengths, cdf, relabel, seed, tag, b0 = args
+    gb = _rng(0xC0DE, tag, seed, b0)
+    d, rk = _distinct_draws(lengths, cdf, gb)
+    words = relabel[rk]
+    order = np.lexsort((words, d))
+    return words[order].astype(np.int32)
+
+
 def corpus(n: int, m: int, median_len: float, sigma: float, max_len: int,
-           zipf_s: float, geom_p: float, seed: int, tag: int = 0, doc_block: int = 200_000):
+           zipf_s: float, geom_p: float, seed: int, tag: int = 0, doc_block: int = 200_000,
+           workers: int = 1, progress=None):
     """Document-like counts V (n words x m documents).
 
     * distinct words per document L ~ round(LogNormal(ln median_len, sigma)), clipped to
@@ -209,6 +219,8 @@ def corpus(n: int, m: int, median_len: float, sigma: float, max_len: int,
     * ranks relabelled to word ids by one seeded random permutation (heavy rows are not
       contiguous);
     * counts 1 + Geometric_0(geom_p), i.e. numpy's geometric(p) on {1, 2, ...}.
+    Documents are drawn in blocks of ``doc_block`` with a seed of their own, so ``workers``
+    > 1 (forked processes; call before the process uses a GPU) gives the same result.
     Returns (csc_ptr, csc_idx, csc_val).
     """
     g = _rng(0xC0DE, tag, seed)
@@ -220,13 +232,23 @@ def corpus(n: int, m: int, median_len: float, sigma: float, max_len: int,
     np.cumsum(lengths, out=ptr[1:])
     nnz = int(ptr[-1])
     idx = np.empty(nnz, dtype=np.int32)
-    for b0 in range(0, m, doc_block):
+    blocks = list(range(0, m, doc_block))
+    jobs = [(lengths[b0:min(m, b0 + doc_block)], cdf, relabel, seed, tag, b0) for b0 in blocks]
+    if workers <= 1 or len(blocks) == 1:
+        results = map(_corpus_block, jobs)
+        pool = None
+    else:
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        pool = cf.ProcessPoolExecutor(max_workers=min(workers, len(blocks)), mp_context=mp.get_context("fork"))
+        results = pool.map(_corpus_block, jobs)
+    for k, (b0, words) in enumerate(zip(blocks, results)):
         b1 = min(m, b0 + doc_block)
-        gb = _rng(0xC0DE, tag, seed, b0)
-        d, rk = _distinct_draws(lengths[b0:b1], cdf, gb)
-        words = relabel[rk]
-        order = np.lexsort((words, d))
-        idx[ptr[b0]:ptr[b1]] = words[order].astype(np.int32)
+        idx[ptr[b0]:ptr[b1]] = words
+        if progress:
+            progress(f"documents {b1} of {m} drawn")
+    if pool is not None:
+        pool.shutdown()
     gv = _rng(0xC0DF, tag, seed)
     val = gv.geometric(geom_p, nnz).astype(np.float32)
     return ptr, idx, val
@@ -263,7 +285,10 @@ def config(i: int, seed: int = 0, **overrides) -> Problem:
         n = overrides.get("n", n)
         m = overrides.get("m", m)
         r = overrides.get("r", r)
-        ptr, idx, val = corpus(n, m, med, 1.0, 2000, 1.1, 0.6, seed, tag=i)
+        ptr, idx, val = corpus(n, m, med, 1.0, 2000, 1.1, 0.6, seed, tag=i,
+                               workers=overrides.get("workers", 1), progress=overrides.get("progress"))
+        if overrides.get("progress"):
+            overrides["progress"]("CSR copy")
         return _problem(n, m, r, ptr, idx, val, seed, i,
                         {"name": CONFIG_NAMES[i] if (n, m) == ((50_000, 100_000) if i == 1 else (100_000, 2_000_000)) else f"corpus {n}x{m} r={r}",
                          "sweeps": sweeps})

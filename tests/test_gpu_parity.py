@@ -327,3 +327,75 @@ def test_ablation_step_parity(flags):
     Fg = gpu_half(prob, prob.W0, prob.F0, t, "F", P.nmfkl_params_default(**flags))
     print(f"ablation {flags}: F rel {relf(Fg, Fo):.2e} flips {flips(Fg, Fo)}")
     assert relf(Fg, Fo) <= 1e-4
+
+
+def _bf16_round(a):
+    """Round float32 values to the nearest bfloat16 (ties to even), kept as float32."""
+    u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32)
+
+
+def test_bf16_tiles_exact_when_the_fixed_factor_is_representable():
+    """With every fixed-factor entry a bfloat16 value, bf16-stored tiles lose nothing: the
+    half-sweep must equal the float32-tile half-sweep up to the summation order of the model
+    values (float64 sums of the same exact products: pins the bf16 copy, its column sums,
+    the tile loads and the model computed from the tiles)."""
+    prob = mid_corpus()
+    W = _bf16_round(prob.W0)
+    F = _bf16_round(prob.F0)
+    for half in ("F", "W"):
+        a = gpu_half(prob, W, F, 2, half, P.nmfkl_params_default())
+        b = gpu_half(prob, W, F, 2, half, P.nmfkl_params_default(tile_bf16=1))
+        e = relf(b, a.astype(np.float64))
+        print(f"bf16 tiles on bf16-representable {half}-half input: rel {e:.2e}, flips {flips(a, b)}")
+        assert e <= 1e-6, f"{half}-half differs with bf16 tiles"
+
+
+def test_bf16_tiles_trajectory_error():
+    """bf16-stored tiles (float32/float64 arithmetic): the objective stays within 1e-3
+    relative of the float32-tile run over 8 sweeps and keeps decreasing."""
+    prob = mid_corpus()
+    D = {}
+    for bf in (0, 1):
+        dev = P.upload(prob, "cuda")
+        h = P.nmfkl_create(dev, P.nmfkl_params_default(tile_bf16=bf))
+        D[bf] = []
+        for t in range(8):
+            P.nmfkl_sweep_F(h, t)
+            P.nmfkl_sweep_W(h, t)
+            D[bf].append(P.nmfkl_objective(h))
+        P.nmfkl_destroy(h)
+    rel = np.abs(np.array(D[1]) - D[0]) / np.array(D[0])
+    print(f"bf16 tiles: objective rel diff per sweep {np.array2string(rel, precision=1)}")
+    assert rel.max() <= 1e-3
+    assert all(D[1][i + 1] <= D[1][i] * (1 + 1e-4) for i in range(7))
+
+
+def huge_row_problem(m=1_700_000, r=4, seed=0):
+    """Row 0 has a nonzero in every column (m nonzeros: more than the co-resident capacity at
+    2048 nonzeros per block), row 1 in every 7th column, row 2 in every 11th."""
+    g = np.random.default_rng(seed)
+    rows, cols = [np.zeros(m, np.int64)], [np.arange(m)]
+    for i, step in ((1, 7), (2, 11)):
+        c = np.arange(0, m, step)
+        rows.append(np.full(c.size, i)); cols.append(c)
+    rows, cols = np.concatenate(rows), np.concatenate(cols)
+    order = np.lexsort((rows, cols))
+    rows, cols = rows[order], cols[order]
+    ptr = np.zeros(m + 1, np.int64)
+    np.cumsum(np.bincount(cols, minlength=m), out=ptr[1:])
+    val = g.geometric(0.6, rows.size).astype(np.float32)
+    return workloads._problem(3, m, r, ptr, rows.astype(np.int32), val, seed, 11, {"name": "huge row"})
+
+
+def test_huge_row_uses_the_wide_kernel_and_matches_the_oracle():
+    prob = huge_row_problem()
+    assert np.diff(prob.csr_ptr).max() > 768 * 2048
+    t = 0
+    ids = oracle.permutation(0, t, 0, prob.r)
+    Wo, _, _ = oracle.sweep_W(prob, prob.F0.astype(np.float64), prob.W0.astype(np.float64), ids)
+    Wg = gpu_half(prob, prob.W0, prob.F0, t, "W")
+    e = relf(Wg, Wo)
+    print(f"huge row W-half: rel {e:.2e}; rows {Wg.tolist()}")
+    assert e <= 1e-4
