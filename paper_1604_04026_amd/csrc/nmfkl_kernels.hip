@@ -700,16 +700,20 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool 
 constexpr int kFusedCW = 8;
 
 template <int G, int E, bool LA>
-__device__ __forceinline__ void sweep_block(const SweepArgs& a, const BlockWork& wk, const int32_t* segs,
-                                            float* xs_all, float* red_lds) {
+__device__ __forceinline__ void sweep_block(const SweepArgs& ag, const BlockWork& wk, const int32_t* segs,
+                                            float* xs_all, float* red_lds, double* sA_lds) {
     const int slot = threadIdx.x / G;
     const int lane = threadIdx.x % G;
     const bool active = slot < wk.count;
     const int seg = active ? segs[wk.first + slot] : 0;
     float* xs = xs_all + slot * NMFKL_R_MAX;
-    // x of the segment, permuted into this sweep's order
+    // x of the segment, permuted into this sweep's order; the column sums in LDS (every
+    // coordinate step reads one, and the block's segments share them)
     if (active)
-        for (int s = lane; s < a.r; s += G) xs[s] = a.X[(int64_t)seg * a.r + a.ids[s]];
+        for (int s = lane; s < ag.r; s += G) xs[s] = ag.X[(int64_t)seg * ag.r + ag.ids[s]];
+    for (int s = threadIdx.x; s < ag.r; s += kFusedThreads) sA_lds[s] = ag.sumA[s];
+    SweepArgs a = ag;
+    a.sumA = sA_lds;
     __syncthreads();
     RegElems<E> st;
     if constexpr (G <= 64) {
@@ -734,14 +738,15 @@ k_sweep_fused(const SweepArgs* __restrict__ tab, const BlockWork* __restrict__ w
               const int32_t* __restrict__ segs) {
     __shared__ float xs_all[(kFusedThreads / 8) * NMFKL_R_MAX];
     __shared__ float red[2 * (kFusedThreads / 64) * kMaxRed];
+    __shared__ double sA_lds[NMFKL_R_MAX];
     const BlockWork wk = work[blockIdx.x];
     const SweepArgs a = tab[wk.prob];
     switch (wk.variant) {
-        case 0: sweep_block<8, 4, false>(a, wk, segs, xs_all, red); break;
-        case 1: sweep_block<16, 4, false>(a, wk, segs, xs_all, red); break;
-        case 2: sweep_block<32, 4, false>(a, wk, segs, xs_all, red); break;
-        case 3: sweep_block<64, 4, false>(a, wk, segs, xs_all, red); break;
-        default: sweep_block<256, 4, LA256>(a, wk, segs, xs_all, red); break;
+        case 0: sweep_block<8, 4, false>(a, wk, segs, xs_all, red, sA_lds); break;
+        case 1: sweep_block<16, 4, false>(a, wk, segs, xs_all, red, sA_lds); break;
+        case 2: sweep_block<32, 4, false>(a, wk, segs, xs_all, red, sA_lds); break;
+        case 3: sweep_block<64, 4, false>(a, wk, segs, xs_all, red, sA_lds); break;
+        default: sweep_block<256, 4, LA256>(a, wk, segs, xs_all, red, sA_lds); break;
     }
 }
 
@@ -776,13 +781,18 @@ k_sweep_long(const SweepArgs* __restrict__ tab, const LongWork* __restrict__ wor
     __shared__ double bcast[kMaxRed];
     __shared__ int32_t s_id[CAP];
     __shared__ float s_v[CAP];
+    __shared__ double sA_lds[NMFKL_R_MAX];
     const LongWork wk = work[blockIdx.x];
-    const SweepArgs a = tab[wk.prob];
+    SweepArgs a = tab[wk.prob];
     const int lane = threadIdx.x;
     LdsElemsNoWU<E, kLongThreads> st;
     st.idp = s_id + lane;
     st.vp = s_v + lane;
-    for (int s = lane; s < a.r; s += kLongThreads) xs[s] = a.X[(int64_t)wk.seg * a.r + a.ids[s]];
+    for (int s = lane; s < a.r; s += kLongThreads) {
+        xs[s] = a.X[(int64_t)wk.seg * a.r + a.ids[s]];
+        sA_lds[s] = a.sumA[s];
+    }
+    a.sumA = sA_lds;
     __syncthreads();
     if constexpr (COOP) {
         CoopReducer<kLongThreads> red;
@@ -980,10 +990,14 @@ k_foldin(FoldinArgs f, SweepArgs a, const int32_t* __restrict__ docs, int ndocs)
     __shared__ int32_t perm_all[SPB * NMFKL_R_MAX];
     __shared__ float red[2 * (kFusedThreads / 64) * kMaxRed];
     __shared__ double red64[2 * (kFusedThreads / 64)];
+    __shared__ double sA_lds[NMFKL_R_MAX];
     const int slot = threadIdx.x / G, lane = threadIdx.x % G;
     const int di = blockIdx.x * SPB + slot;
     const bool active = di < ndocs;
     const int d = active ? docs[di] : 0;
+    for (int k = threadIdx.x; k < a.r; k += kFusedThreads) sA_lds[k] = a.sumA[k];
+    __syncthreads();
+    a.sumA = sA_lds;
     RegElems<E> st;
     if constexpr (G <= 64) {
         WaveReducer<G> rd;
@@ -1007,9 +1021,13 @@ k_foldin_block(FoldinArgs f, SweepArgs a, const int32_t* __restrict__ docs, int 
     __shared__ double red64[2 * (G / 64)];
     __shared__ int32_t s_id[G * E];
     __shared__ float s_v[G * E], s_w[G * E], s_u[G * E];
+    __shared__ double sA_lds[NMFKL_R_MAX];
     const bool active = (int)blockIdx.x < ndocs;
     const int d = active ? docs[blockIdx.x] : 0;
     const int lane = threadIdx.x;
+    for (int k = lane; k < a.r; k += G) sA_lds[k] = a.sumA[k];
+    __syncthreads();
+    a.sumA = sA_lds;
     BlockReducer<G> rd{red, 0, red64};
     LdsElems<E, G> st;
     st.idp = s_id + lane;
