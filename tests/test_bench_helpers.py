@@ -1,0 +1,50 @@
+"""Host-side helpers of bench.py: the HBM-traffic summary from rocprofv3 counter files."""
+import csv
+import json
+import os
+
+import pytest
+
+import bench
+
+FIELDS = ["Correlation_Id", "Dispatch_Id", "Agent_Id", "Queue_Id", "Process_Id", "Thread_Id", "Grid_Size",
+          "Kernel_Id", "Kernel_Name", "Workgroup_Size", "LDS_Block_Size", "Scratch_Size", "VGPR_Count",
+          "Accum_VGPR_Count", "SGPR_Count", "Counter_Name", "Counter_Value", "Start_Timestamp", "End_Timestamp"]
+
+
+def _write(path, counter, copy_kib, fused_kib, terms_kib):
+    os.makedirs(path, exist_ok=True)
+    rows, d = [], 0
+
+    def add(name, v):
+        nonlocal d
+        d += 1
+        rows.append({**{f: 0 for f in FIELDS}, "Dispatch_Id": d, "Kernel_Name": name, "Counter_Name": counter,
+                     "Counter_Value": v})
+    for _ in range(3):
+        add("__amd_rocclr_copyBuffer", copy_kib)
+    for sweep in range(4):               # F-half and W-half binned launches, then the terms
+        add("void nmfkl::k_sweep_fused<false>(...)", fused_kib[0])
+        add("void nmfkl::k_sweep_fused<false>(...)", fused_kib[1])
+        add("nmfkl::k_model_terms(...)", terms_kib)
+    with open(os.path.join(path, "run_counter_collection.csv"), "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=FIELDS)
+        w.writeheader()
+        w.writerows(rows)
+
+
+def test_traffic_summary_scales_by_the_copy(tmp_path):
+    half = bench.COPY_BYTES / 1024 / 2          # a counter that sees half the bytes
+    _write(tmp_path / "f", "FETCH_SIZE", half, (1000.0, 500.0), 100.0)
+    _write(tmp_path / "w", "WRITE_SIZE", 2 * half, (80.0, 40.0), 1.0)
+    out = tmp_path / "traffic.json"
+    bench.traffic_summarize(str(tmp_path / "f"), str(tmp_path / "w"), str(out))
+    t = json.loads(out.read_text())
+    assert t["calibration"]["fetch_scale"] == pytest.approx(2.0)
+    assert t["calibration"]["write_scale"] == pytest.approx(1.0)
+    g = t["groups"]
+    assert g["fused_F"]["fetch_bytes_per_launch"] == pytest.approx(2000.0 * 1024)
+    assert g["fused_W"]["fetch_bytes_per_launch"] == pytest.approx(1000.0 * 1024)
+    assert g["fused_F"]["hbm_bytes_per_launch"] == pytest.approx((2000.0 + 80.0) * 1024)
+    assert g["terms"]["fetch_bytes_per_launch"] == pytest.approx(200.0 * 1024)
+    assert t["kernel_source_sha256_16"] == bench.source_hash()

@@ -55,3 +55,16 @@ def test_generation_is_deterministic():
     assert np.array_equal(a.csc_idx, b.csc_idx) and np.array_equal(a.W0, b.W0)
     c = workloads.config(0, seed=6)
     assert not np.array_equal(a.W0, c.W0)
+
+
+def test_parallel_generation_is_identical():
+    """Document blocks carry their own seeds: forked workers give the same corpus, and the
+    batched members are the same whether generated serially or in workers."""
+    a = workloads.corpus(1500, 24000, 80.0, 1.0, 2000, 1.1, 0.6, seed=3, tag=5, doc_block=5000)
+    b = workloads.corpus(1500, 24000, 80.0, 1.0, 2000, 1.1, 0.6, seed=3, tag=5, doc_block=5000, workers=3)
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+    p = workloads.batched_configs(seed=1, count=3, scale=0.05)
+    q = workloads.batched_configs(seed=1, count=3, scale=0.05, workers=3)
+    for x, y in zip(p, q):
+        assert np.array_equal(x.csc_idx, y.csc_idx) and np.array_equal(x.csr_val, y.csr_val)
+        assert np.array_equal(x.W0, y.W0) and np.array_equal(x.F0, y.F0)
