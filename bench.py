@@ -80,10 +80,19 @@ def cpu_baseline(prob, seconds: float):
         if time.perf_counter() - t0 >= seconds or sweeps >= 60:
             break
     dt = time.perf_counter() - t0
+    # the same oracle on one core: the F-half of the first sweep
+    threads = oracle.threads()
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    oracle.sweep_F(prob, prob.W0.astype(np.float64), prob.F0.astype(np.float64), oracle.permutation(0, 0, 0, prob.r))
+    d1 = time.perf_counter() - t1
+    oracle.set_threads(threads)
     return {"value": 2.0 * prob.nnz * prob.r * sweeps / dt, "unit": "updates/s",
-            "cores": oracle.threads(), "kind": "oracle",
+            "cores": threads, "kind": "oracle",
             "sample": f"{sweeps} full sweeps (F-half + W-half + objective) of the same corpus from "
-                      f"the same initial factors, {dt:.1f} s wall"}, D
+                      f"the same initial factors, {dt:.1f} s wall",
+            "single_core": {"value": prob.nnz * prob.r / d1, "unit": "updates/s", "cores": 1,
+                            "sample": f"the first F-half on one thread, {d1:.1f} s wall"}}, D
 
 
 def sweep_leg(P, prob, args, log):
@@ -419,6 +428,40 @@ def large_run(args, log):
     print(json.dumps(out), flush=True)
 
 
+def ablation_run(args, log):
+    """The inner-loop readings and the L1 weight on the corpus, 10 outer iterations each from
+    the same initial factors: objective (eq. 1) and the fraction of exact zeros in W and F.
+    Settings: the build's reading (|step| break test, descent guard); the signed break test as
+    printed; no guard; both as printed; and L1 weights beta_W = beta_F in {10, 100, 1000}."""
+    from paper_1604_04026_amd import workloads
+    prob = workloads.config(1, seed=args.seed)
+    import numpy as np
+    import torch
+    import paper_1604_04026_amd as P
+    torch.cuda.set_device(0)
+    settings = [("reading (|step| break, guard)", {}), ("signed break as printed", {"literal_break": 1}),
+                ("no descent guard", {"guard": 0}), ("signed break, no guard", {"literal_break": 1, "guard": 0})]
+    settings += [(f"L1 beta_W = beta_F = {b:g}", {"beta_W": b, "beta_F": b}) for b in (10.0, 100.0, 1000.0)]
+    out = {"workload": "doc-like corpus 50000x100000 r=50", "sweeps": 10, "runs": []}
+    for name, kw in settings:
+        dev = P.upload(prob, "cuda:0")
+        h = P.nmfkl_create(dev, P.nmfkl_params_default(seed=args.seed, collect_stats=1, **kw))
+        D = []
+        for t in range(10):
+            P.nmfkl_sweep_F(h, t)
+            P.nmfkl_sweep_W(h, t)
+            D.append(P.nmfkl_objective(h))
+        st = P.nmfkl_get_stats(h)
+        W, F = dev.W.cpu().numpy(), dev.F.cpu().numpy()
+        P.nmfkl_destroy(h)
+        rec = {"setting": name, "params": kw, "objective": D, "zeros_W": float(np.mean(W == 0)),
+               "zeros_F": float(np.mean(F == 0)), "monotone": all(D[i + 1] <= D[i] for i in range(9)),
+               "stats": st}
+        log(f"[ablation] {name}: D10 {D[-1]:.6g} zeros W {rec['zeros_W']:.3f} F {rec['zeros_F']:.3f}")
+        out["runs"].append(rec)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     if len(sys.argv) >= 2 and sys.argv[1] == "--traffic-summarize":
         traffic_summarize(sys.argv[2], sys.argv[3], sys.argv[4])
@@ -441,6 +484,8 @@ def main():
                     help="the command profiled for HBM traffic (calibration copy + sweeps only)")
     ap.add_argument("--large", action="store_true",
                     help="the large corpus (100,000 x 2,000,000, r = 100): float32 vs bf16 tiles")
+    ap.add_argument("--ablation", action="store_true",
+                    help="inner-loop readings and L1 weights on the corpus: objective and exact zeros")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sweep's sharding over "
@@ -448,6 +493,9 @@ def main():
         sys.exit(2)
     if args.traffic_run:
         traffic_run(args)
+        return
+    if args.ablation:
+        ablation_run(args, (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True)))
         return
     if args.large:
         large_run(args, (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True)))
