@@ -91,11 +91,21 @@ typedef struct nmfkl_params {
                                   float32 / float64).  Halves the bytes of each tile gather; results
                                   differ from float32 tiles by the rounding (about 2^-9 relative per
                                   factor entry) */
+    int32_t out_of_core;       /* 0 (default): V's CSC/CSR arrays are device memory.  1: they are host
+                                  memory (pinned, e.g. hipHostMalloc, for overlapped copies) and every
+                                  half-sweep streams them through two device staging buffers in
+                                  chunks of whole columns/rows, copying the next chunk while the
+                                  current one is swept; no model values are kept (each column/row
+                                  computes them from the tiles, Alg. 2's first step).  W and F stay
+                                  device memory.  Not available for batches */
+    int64_t ooc_chunk_nnz;     /* out_of_core: nonzeros per chunk (0: 1 << 25); a chunk grows to hold
+                                  a longer column/row */
 } nmfkl_params;
 
 typedef struct nmfkl_problem {
     int32_t n, m, r;           /* V is n x m, rank r (1 <= r <= NMFKL_R_MAX) */
     int64_t nnz;               /* number of stored entries (same in both copies) */
+    /* the six V arrays are host memory instead when params.out_of_core = 1 */
     const int64_t* csc_ptr;    /* (device) m+1 */
     const int32_t* csc_idx;    /* (device) nnz row ids */
     const float* csc_val;      /* (device) nnz */
@@ -158,8 +168,11 @@ int nmfkl_permutation(uint64_t seed, uint64_t t, uint64_t stream, int32_t r, int
  * the CSC/CSR structure (pointer monotonicity and ends, index ranges and strict order,
  * values finite and >= 0, CSR equal to the transpose of CSC) and W, F finite and >= 0;
  * synchronises the stream once.  Builds the nnz bins, the CSC<->CSR position maps and the
- * scratch buffers.  Errors: NMFKL_E_INVAL (shape/structure/value), NMFKL_E_NOMEM,
- * NMFKL_E_DEVICE.  On error *out is NULL. */
+ * scratch buffers.  With params.out_of_core the structure and values are validated on the
+ * host (the transpose by per-row counts and an order-independent checksum of the entries),
+ * the bins are built per chunk and no maps or model values are allocated.  Errors:
+ * NMFKL_E_INVAL (shape/structure/value), NMFKL_E_NOMEM, NMFKL_E_DEVICE.  On error *out is
+ * NULL. */
 int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_stream,
                  nmfkl_handle** out);
 

@@ -18,7 +18,7 @@ __all__ = [
     "NmfklError", "NmfklParams", "NmfklProblem", "NmfklStats", "load", "nmfkl_params_default",
     "nmfkl_permutation", "nmfkl_create", "nmfkl_sweep_F", "nmfkl_sweep_W", "nmfkl_objective",
     "nmfkl_invalidate_model", "nmfkl_get_stats", "nmfkl_get_timings", "nmfkl_reset_timings",
-    "nmfkl_destroy", "nmfkl_last_error", "DeviceProblem", "upload", "Handle", "EXPORTED_SYMBOLS",
+    "nmfkl_destroy", "nmfkl_last_error", "DeviceProblem", "upload", "upload_host_v", "Handle", "EXPORTED_SYMBOLS",
 ]
 
 NMFKL_OK = 0
@@ -57,6 +57,7 @@ class NmfklParams(ctypes.Structure):
         ("refresh_model", ctypes.c_int32), ("collect_stats", ctypes.c_int32),
         ("collect_timings", ctypes.c_int32), ("tuning", ctypes.c_int32),
         ("bin_shift", ctypes.c_int32), ("tile_bf16", ctypes.c_int32),
+        ("out_of_core", ctypes.c_int32), ("ooc_chunk_nnz", ctypes.c_int64),
     ]
 
 
@@ -207,17 +208,20 @@ def _stream_ptr(stream) -> int:
 class DeviceProblem:
     """Device copies (torch tensors) of V in CSC and CSR form and of the two factors."""
 
-    def __init__(self, n, m, r, csc_ptr, csc_idx, csc_val, csr_ptr, csr_idx, csr_val, W, F):
+    def __init__(self, n, m, r, csc_ptr, csc_idx, csc_val, csr_ptr, csr_idx, csr_val, W, F, host_v=False):
         self.n, self.m, self.r = int(n), int(m), int(r)
         self.csc_ptr, self.csc_idx, self.csc_val = csc_ptr, csc_idx, csc_val
         self.csr_ptr, self.csr_idx, self.csr_val = csr_ptr, csr_idx, csr_val
         self.W, self.F = W, F
+        self.host_v = host_v
         import torch
-        for t, dt in ((csc_ptr, torch.int64), (csc_idx, torch.int32), (csc_val, torch.float32),
-                      (csr_ptr, torch.int64), (csr_idx, torch.int32), (csr_val, torch.float32),
-                      (W, torch.float32), (F, torch.float32)):
-            if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
-                raise ValueError(f"expected a contiguous {dt} device tensor, got {t.dtype} on {t.device}")
+        for k, (t, dt) in enumerate(((csc_ptr, torch.int64), (csc_idx, torch.int32), (csc_val, torch.float32),
+                                     (csr_ptr, torch.int64), (csr_idx, torch.int32), (csr_val, torch.float32),
+                                     (W, torch.float32), (F, torch.float32))):
+            on_device = not (host_v and k < 6)
+            if t.dtype != dt or t.is_cuda != on_device or not t.is_contiguous():
+                where = "device" if on_device else "host"
+                raise ValueError(f"expected a contiguous {dt} {where} tensor, got {t.dtype} on {t.device}")
         if tuple(W.shape) != (self.n, self.r) or tuple(F.shape) != (self.m, self.r):
             raise ValueError("W must be n x r and F m x r")
 
@@ -240,6 +244,18 @@ def upload(prob, device="cuda", W=None, F=None) -> DeviceProblem:
                          t(prob.csr_ptr), t(prob.csr_idx), t(prob.csr_val),
                          t(np.asarray(prob.W0 if W is None else W, np.float32)),
                          t(np.asarray(prob.F0 if F is None else F, np.float32)))
+
+
+def upload_host_v(prob, device="cuda", W=None, F=None) -> DeviceProblem:
+    """V's six arrays in pinned host memory (for params.out_of_core = 1), the factors on the
+    device."""
+    import torch
+    h = lambda a: torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+    return DeviceProblem(prob.n, prob.m, prob.r, h(prob.csc_ptr), h(prob.csc_idx), h(prob.csc_val),
+                         h(prob.csr_ptr), h(prob.csr_idx), h(prob.csr_val),
+                         d(np.asarray(prob.W0 if W is None else W, np.float32)),
+                         d(np.asarray(prob.F0 if F is None else F, np.float32)), host_v=True)
 
 
 class Handle:
@@ -266,6 +282,8 @@ def nmfkl_create(dev: DeviceProblem, params: NmfklParams | None = None, stream=N
     out = ctypes.c_void_p()
     prob = dev.struct()
     prm = params if params is not None else nmfkl_params_default()
+    if bool(prm.out_of_core) != bool(getattr(dev, "host_v", False)):
+        raise ValueError("params.out_of_core = 1 takes V in host memory (upload_host_v); 0 takes it on the device")
     _check(load().nmfkl_create(ctypes.byref(prob), ctypes.byref(prm), _stream_ptr(stream),
                                ctypes.byref(out)))
     return Handle(out.value, dev, stream)

@@ -76,6 +76,26 @@ struct nmfkl_handle {
     int huge_capacity = 0;             // ... of the huge-segment kernel
     BinPlan binF, binW;
     std::vector<int64_t> hptr_csc, hptr_csr;  // host copies of the segment pointers
+    // out-of-core V (params.out_of_core): chunks of whole columns (F-half) / rows (W-half)
+    // streamed from host memory through two device staging buffers
+    struct Chunk {
+        int64_t seg0, seg1;        // segment range
+        int64_t nnz0, nnz1;        // nonzero range
+        int64_t lptr;              // offset of its rebased pointers in h_lptr
+        BinPlan plan;
+    };
+    bool ooc = false;
+    std::vector<Chunk> chunks[2];  // [0] columns (CSC), [1] rows (CSR)
+    int64_t* h_lptr = nullptr;     // pinned host: rebased pointers of every chunk of both halves
+    int64_t* d_ptr[2] = {nullptr, nullptr};
+    int32_t* d_idx[2] = {nullptr, nullptr};
+    float* d_val[2] = {nullptr, nullptr};
+    SweepArgs* ooc_args = nullptr;  // device: one entry per chunk (half 0 chunks, then half 1)
+    double* d_chunk_obj = nullptr;  // per-chunk objective partial sums
+    hipStream_t copy_stream = nullptr;
+    hipEvent_t ev_copied[2] = {nullptr, nullptr}, ev_used[2] = {nullptr, nullptr};
+    bool used_recorded[2] = {false, false};
+    int64_t staged_bytes = 0;       // H2D bytes of V moved (timing/measurement)
     SweepArgs* argtab = nullptr;       // device: kNumArgs sweep-argument entries
     PermJob* jobtab = nullptr;         // device: kNumJobs permute jobs
     // timing (params.collect_timings): event pairs per launch group, resolved on demand
@@ -166,6 +186,18 @@ void release(nmfkl_handle* h) {
     f(h->binF.long_work); f(h->binW.long_work);
     f(h->coop_words); f(h->dev_err); f(h->argtab); f(h->jobtab);
     if (h->host_scal) (void)hipHostFree(h->host_scal);
+    for (int k = 0; k < 2; ++k) {
+        for (auto& c : h->chunks[k]) {
+            auto g = [](void* q) { if (q) (void)hipFree(q); };
+            g(c.plan.work); g(c.plan.segs); g(c.plan.long_work);
+        }
+        f(h->d_ptr[k]); f(h->d_idx[k]); f(h->d_val[k]);
+        if (h->ev_copied[k]) (void)hipEventDestroy(h->ev_copied[k]);
+        if (h->ev_used[k]) (void)hipEventDestroy(h->ev_used[k]);
+    }
+    f(h->ooc_args); f(h->d_chunk_obj);
+    if (h->h_lptr) (void)hipHostFree(h->h_lptr);
+    if (h->copy_stream) (void)hipStreamDestroy(h->copy_stream);
 }
 
 // Variant for a segment of length L in the fused launch (-1: too long).  bin_shift > 0 maps
@@ -328,6 +360,8 @@ int check_params(const nmfkl_params* p, std::string* why) {
     if (!(p->foldin_tol >= 0)) return bad("foldin_tol must be >= 0");
     if (p->bin_shift < 0 || p->bin_shift > 3) return bad("bin_shift must be in [0, 3]");
     if (p->tile_bf16 != 0 && p->tile_bf16 != 1) return bad("tile_bf16 must be 0 or 1");
+    if (p->out_of_core != 0 && p->out_of_core != 1) return bad("out_of_core must be 0 or 1");
+    if (p->ooc_chunk_nnz < 0) return bad("ooc_chunk_nnz must be >= 0");
     return NMFKL_OK;
 }
 
@@ -354,6 +388,7 @@ SweepArgs sweep_args(nmfkl_handle* h, bool fhalf) {
     a.literal_break = h->prm.literal_break;
     a.guard = h->prm.guard;
     a.tile_bf16 = h->prm.tile_bf16;
+    a.model_from_tiles = h->prm.tile_bf16 || h->prm.out_of_core;
     return a;
 }
 
@@ -436,9 +471,63 @@ hipError_t enqueue_plan(const BinPlan& plan, const SweepArgs* tab, unsigned long
     return hipSuccess;
 }
 
+// Out-of-core V: stage chunk c of half `half` into buffer c % 2 on the copy stream, once the
+// kernels that last used that buffer are done, and make the handle's stream wait for it.
+hipError_t ooc_stage(nmfkl_handle* h, int half, size_t c) {
+    const auto& ch = h->chunks[half][c];
+    const nmfkl_problem& pr = h->prob;
+    const int b = (int)(c & 1);
+    const int32_t* idx = half == 0 ? pr.csc_idx : pr.csr_idx;
+    const float* val = half == 0 ? pr.csc_val : pr.csr_val;
+    const int64_t nseg = ch.seg1 - ch.seg0, nnz = ch.nnz1 - ch.nnz0;
+    hipError_t e;
+    if (h->used_recorded[b] && (e = hipStreamWaitEvent(h->copy_stream, h->ev_used[b], 0)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(h->d_ptr[b], h->h_lptr + ch.lptr, (size_t)(nseg + 1) * sizeof(int64_t),
+                            hipMemcpyHostToDevice, h->copy_stream)) != hipSuccess)
+        return e;
+    if (nnz > 0) {
+        if ((e = hipMemcpyAsync(h->d_idx[b], idx + ch.nnz0, (size_t)nnz * sizeof(int32_t), hipMemcpyHostToDevice,
+                                h->copy_stream)) != hipSuccess)
+            return e;
+        if ((e = hipMemcpyAsync(h->d_val[b], val + ch.nnz0, (size_t)nnz * sizeof(float), hipMemcpyHostToDevice,
+                                h->copy_stream)) != hipSuccess)
+            return e;
+    }
+    if ((e = hipEventRecord(h->ev_copied[b], h->copy_stream)) != hipSuccess) return e;
+    h->staged_bytes += (nseg + 1) * 8 + nnz * 8;
+    return hipStreamWaitEvent(h->stream, h->ev_copied[b], 0);
+}
+
+hipError_t ooc_release(nmfkl_handle* h, size_t c) {
+    const int b = (int)(c & 1);
+    h->used_recorded[b] = true;
+    return hipEventRecord(h->ev_used[b], h->stream);
+}
+
+int half_sweep_ooc(nmfkl_handle* h, int32_t t, bool fhalf) {
+    const nmfkl_problem& pr = h->prob;
+    const int half = fhalf ? 0 : 1;
+    const int ts = timer_begin(h, fhalf ? NMFKL_T_SUMS_F : NMFKL_T_SUMS_W);
+    const PermJob* job = h->jobtab + (fhalf ? kJobF : kJobW);
+    HIP_TRY(h, launch_permute_jobs(job, 1, h->sum_blocks, t, nullptr, h->stream));
+    HIP_TRY(h, launch_finalize_jobs(job, 1, pr.r, h->stream));
+    timer_end(h, ts);
+    const size_t first = fhalf ? 0 : h->chunks[0].size();
+    for (size_t c = 0; c < h->chunks[half].size(); ++c) {
+        HIP_TRY(h, ooc_stage(h, half, c));
+        HIP_TRY(h, enqueue_plan(h->chunks[half][c].plan, h->ooc_args + first + c, h->coop_words, h->dev_err, true,
+                                (h->prm.tuning & 1) != 0, h->stream, h, fhalf ? NMFKL_T_LONG_F : NMFKL_T_LONG_W,
+                                fhalf ? NMFKL_T_FUSED_F : NMFKL_T_FUSED_W));
+        HIP_TRY(h, ooc_release(h, c));
+    }
+    h->model = kModelNone;
+    return NMFKL_OK;
+}
+
 int half_sweep(nmfkl_handle* h, int32_t t, bool fhalf) {
     if (!h) return fail(nullptr, NMFKL_E_INVAL, "null handle");
     if (t < 0) return fail(h, NMFKL_E_INVAL, "t must be >= 0");
+    if (h->ooc) return half_sweep_ooc(h, t, fhalf);
     const nmfkl_problem& pr = h->prob;
     const BinPlan& plan = fhalf ? h->binF : h->binW;
     if (h->prm.tile_bf16) {
@@ -504,6 +593,221 @@ const char* nmfkl_last_error(const nmfkl_handle* h) {
     return h ? h->err.c_str() : g_create_error.c_str();
 }
 
+}  // extern "C"
+
+namespace {
+
+// Host-side validation of V for the out-of-core mode: pointer arrays, index ranges and
+// strict order, values; the CSR copy is the transpose of the CSC copy if every row count
+// agrees and an order-independent checksum of the (row, column, value) entries agrees.
+std::string validate_host_v(const nmfkl_problem& pr) {
+    auto check_ptr = [](const int64_t* ptr, int64_t Q, int64_t nnz) {
+        if (ptr[0] != 0 || ptr[Q] != nnz) return false;
+        for (int64_t q = 0; q < Q; ++q)
+            if (ptr[q + 1] < ptr[q]) return false;
+        return true;
+    };
+    if (!check_ptr(pr.csc_ptr, pr.m, pr.nnz) || !check_ptr(pr.csr_ptr, pr.n, pr.nnz))
+        return "pointer array not monotone / wrong ends";
+    auto mix = [](uint64_t x) {
+        x ^= x >> 33; x *= 0xFF51AFD7ED558CCDull; x ^= x >> 33; x *= 0xC4CEB9FE1A85EC53ull; x ^= x >> 33;
+        return x;
+    };
+    std::vector<int64_t> rowcount((size_t)pr.n, 0);
+    uint64_t sum_csc = 0, sum_csr = 0;
+    for (int64_t j = 0; j < pr.m; ++j)
+        for (int64_t q = pr.csc_ptr[j]; q < pr.csc_ptr[j + 1]; ++q) {
+            const int32_t i = pr.csc_idx[q];
+            const float v = pr.csc_val[q];
+            if (i < 0 || i >= pr.n) return "index out of range";
+            if (q > pr.csc_ptr[j] && i <= pr.csc_idx[q - 1]) return "indices not strictly increasing within a column";
+            if (!(v >= 0.0f) || !std::isfinite(v)) return "value negative or not finite";
+            rowcount[(size_t)i] += 1;
+            uint32_t vb;
+            std::memcpy(&vb, &v, 4);
+            sum_csc += mix(((uint64_t)i << 32 | (uint64_t)j) ^ mix(vb));
+        }
+    for (int64_t i = 0; i < pr.n; ++i) {
+        if (pr.csr_ptr[i + 1] - pr.csr_ptr[i] != rowcount[(size_t)i]) return "CSR is not the transpose of CSC";
+        for (int64_t q = pr.csr_ptr[i]; q < pr.csr_ptr[i + 1]; ++q) {
+            const int32_t j = pr.csr_idx[q];
+            const float v = pr.csr_val[q];
+            if (j < 0 || j >= pr.m) return "index out of range";
+            if (q > pr.csr_ptr[i] && j <= pr.csr_idx[q - 1]) return "indices not strictly increasing within a row";
+            uint32_t vb;
+            std::memcpy(&vb, &v, 4);
+            sum_csr += mix(((uint64_t)i << 32 | (uint64_t)j) ^ mix(vb));
+        }
+    }
+    if (sum_csc != sum_csr) return "CSR is not the transpose of CSC";
+    return "";
+}
+
+// Chunks of whole segments of at most `budget` nonzeros (a longer segment gets a chunk of its
+// own), with their pointers rebased into `lptr`.
+void make_chunks(const int64_t* ptr, int64_t Q, int64_t budget, std::vector<nmfkl_handle::Chunk>* out,
+                 std::vector<int64_t>* lptr, int64_t* max_nnz, int64_t* max_segs) {
+    int64_t q = 0;
+    while (q < Q) {
+        nmfkl_handle::Chunk c{};
+        c.seg0 = q;
+        c.nnz0 = ptr[q];
+        int64_t q1 = q + 1;
+        while (q1 < Q && ptr[q1 + 1] - c.nnz0 <= budget) ++q1;
+        c.seg1 = q1;
+        c.nnz1 = ptr[q1];
+        c.lptr = (int64_t)lptr->size();
+        for (int64_t k = q; k <= q1; ++k) lptr->push_back(ptr[k] - c.nnz0);
+        *max_nnz = std::max(*max_nnz, c.nnz1 - c.nnz0);
+        *max_segs = std::max(*max_segs, c.seg1 - c.seg0);
+        out->push_back(c);
+        q = q1;
+    }
+}
+
+// True if p is device memory of the current device (or managed memory).
+bool is_device_memory(const void* p) {
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();   // unregistered host memory
+        return false;
+    }
+    return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+}
+
+int create_ooc(const nmfkl_problem& pr, const nmfkl_params& prm, void* hip_stream, nmfkl_handle** out) {
+    for (const void* q : {(const void*)pr.csc_ptr, (const void*)pr.csc_idx, (const void*)pr.csc_val,
+                          (const void*)pr.csr_ptr, (const void*)pr.csr_idx, (const void*)pr.csr_val})
+        if (q && is_device_memory(q))
+            return fail(nullptr, NMFKL_E_INVAL, "out_of_core: V's arrays must be host memory");
+    if (!is_device_memory(pr.W) || !is_device_memory(pr.F))
+        return fail(nullptr, NMFKL_E_INVAL, "W and F must be device memory");
+    std::string why = validate_host_v(pr);
+    if (!why.empty()) return fail(nullptr, NMFKL_E_INVAL, "invalid input: " + why);
+    nmfkl_handle* h = new (std::nothrow) nmfkl_handle();
+    if (!h) return fail(nullptr, NMFKL_E_NOMEM, "host allocation failed");
+    h->prob = pr;
+    h->prm = prm;
+    h->ooc = true;
+    h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    auto bail = [&](int code) {
+        g_create_error = h->err;
+        if (h->stream) (void)hipStreamSynchronize(h->stream);
+        if (h->copy_stream) (void)hipStreamSynchronize(h->copy_stream);
+        release(h);
+        delete h;
+        return code;
+    };
+#define OOC_HIP(expr)                                            \
+    do {                                                         \
+        hipError_t e_ = (expr);                                  \
+        if (e_ != hipSuccess) return bail(hip_fail(h, e_, #expr)); \
+    } while (0)
+    OOC_HIP(hipGetDevice(&h->device));
+    h->Sp = (pr.r + kChunk - 1) / kChunk * kChunk;
+    const int64_t Pmax = std::max<int64_t>(pr.n, pr.m);
+    unsigned* flags = nullptr;
+    OOC_HIP(dalloc(&flags, 1));
+    OOC_HIP(hipMemsetAsync(flags, 0, sizeof(unsigned), h->stream));
+    OOC_HIP(launch_validate_factor(pr.W, (int64_t)pr.n * pr.r, flags, kBadW, h->stream));
+    OOC_HIP(launch_validate_factor(pr.F, (int64_t)pr.m * pr.r, flags, kBadF, h->stream));
+    unsigned hf = 0;
+    OOC_HIP(hipMemcpyAsync(&hf, flags, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));
+    OOC_HIP(hipStreamSynchronize(h->stream));
+    (void)hipFree(flags);
+    if (hf) {
+        fail(h, NMFKL_E_INVAL, std::string("invalid input:") + ((hf & kBadW) ? " W negative or not finite;" : "") +
+                                   ((hf & kBadF) ? " F negative or not finite;" : ""));
+        return bail(NMFKL_E_INVAL);
+    }
+    OOC_HIP(dalloc(&h->Ap, (size_t)Pmax * h->Sp));
+    OOC_HIP(dalloc(&h->sumA, NMFKL_R_MAX));
+    h->sum_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, Pmax / 64));
+    OOC_HIP(dalloc(&h->partials, (size_t)h->sum_blocks * pr.r));
+    OOC_HIP(dalloc(&h->ids, NMFKL_R_MAX));
+    h->obj_blocks = 4096;
+    OOC_HIP(dalloc(&h->obj_partials, h->obj_blocks));
+    OOC_HIP(dalloc(&h->sums2, 2 * (size_t)pr.r));
+    OOC_HIP(dalloc(&h->dscal, 1));
+    OOC_HIP(dalloc(&h->stats, 6));
+    OOC_HIP(hipMemsetAsync(h->stats, 0, 6 * sizeof(unsigned long long), h->stream));
+    OOC_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->host_scal), sizeof(double), hipHostMallocDefault));
+    OOC_HIP(dalloc(&h->dev_err, 1));
+    OOC_HIP(hipMemsetAsync(h->dev_err, 0, sizeof(unsigned), h->stream));
+    int ncu = 0;
+    OOC_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
+    h->long_capacity = long_kernel_blocks_per_cu(false) * ncu;
+    h->huge_capacity = long_kernel_blocks_per_cu(true) * ncu;
+    if (h->long_capacity <= 0 || h->huge_capacity <= 0) {
+        fail(h, NMFKL_E_DEVICE, "occupancy query of the long-segment kernel failed");
+        return bail(NMFKL_E_DEVICE);
+    }
+    // chunks and their bins
+    const int64_t budget = prm.ooc_chunk_nnz > 0 ? prm.ooc_chunk_nnz : ((int64_t)1 << 25);
+    std::vector<int64_t> lptr;
+    int64_t max_nnz = 0, max_segs = 0;
+    make_chunks(pr.csc_ptr, pr.m, budget, &h->chunks[0], &lptr, &max_nnz, &max_segs);
+    make_chunks(pr.csr_ptr, pr.n, budget, &h->chunks[1], &lptr, &max_nnz, &max_segs);
+    int groups = 1, pmax = 1;
+    for (int half = 0; half < 2; ++half)
+        for (auto& c : h->chunks[half]) {
+            std::vector<int64_t> local(lptr.begin() + c.lptr, lptr.begin() + c.lptr + (c.seg1 - c.seg0) + 1);
+            std::string why_plan;
+            const int rc = plan_bins({SegSource{&local, pr.r, 0}}, h->long_capacity, h->huge_capacity, prm.bin_shift,
+                                     false, &c.plan, &why_plan);
+            if (rc) {
+                fail(h, rc, why_plan);
+                return bail(rc);
+            }
+            groups = std::max(groups, c.plan.max_groups);
+            pmax = std::max(pmax, c.plan.max_pmax);
+        }
+    OOC_HIP(dalloc(&h->coop_words, (size_t)groups * 2 * pmax * kCoopValues));
+    OOC_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->h_lptr), lptr.size() * sizeof(int64_t), hipHostMallocDefault));
+    std::memcpy(h->h_lptr, lptr.data(), lptr.size() * sizeof(int64_t));
+    for (int b = 0; b < 2; ++b) {
+        OOC_HIP(dalloc(&h->d_ptr[b], (size_t)max_segs + 1));
+        OOC_HIP(dalloc(&h->d_idx[b], (size_t)max_nnz));
+        OOC_HIP(dalloc(&h->d_val[b], (size_t)max_nnz));
+        OOC_HIP(hipEventCreateWithFlags(&h->ev_copied[b], hipEventDisableTiming));
+        OOC_HIP(hipEventCreateWithFlags(&h->ev_used[b], hipEventDisableTiming));
+    }
+    OOC_HIP(hipStreamCreateWithFlags(&h->copy_stream, hipStreamNonBlocking));
+    OOC_HIP(dalloc(&h->d_chunk_obj, h->chunks[0].size()));
+    {
+        std::vector<SweepArgs> args;
+        for (int half = 0; half < 2; ++half)
+            for (size_t c = 0; c < h->chunks[half].size(); ++c) {
+                SweepArgs a = sweep_args(h, half == 0);
+                const int b = (int)(c & 1);
+                a.ptr = h->d_ptr[b];
+                a.idx = h->d_idx[b];
+                a.val = h->d_val[b];
+                a.X = (half == 0 ? pr.F : pr.W) + h->chunks[half][c].seg0 * pr.r;
+                a.Min = nullptr;
+                a.Mmap = nullptr;
+                a.Mout = nullptr;
+                a.model_from_tiles = 1;
+                args.push_back(a);
+            }
+        OOC_HIP(dalloc(&h->ooc_args, args.size()));
+        OOC_HIP(hipMemcpy(h->ooc_args, args.data(), args.size() * sizeof(SweepArgs), hipMemcpyHostToDevice));
+        PermJob jobs[kNumJobs];
+        make_jobs(h, jobs);
+        OOC_HIP(dalloc(&h->jobtab, kNumJobs));
+        OOC_HIP(hipMemcpy(h->jobtab, jobs, sizeof(jobs), hipMemcpyHostToDevice));
+    }
+    OOC_HIP(hipStreamSynchronize(h->stream));
+#undef OOC_HIP
+    h->model = kModelNone;
+    *out = h;
+    return NMFKL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_stream,
                  nmfkl_handle** out) {
     if (!out) return fail(nullptr, NMFKL_E_INVAL, "out is null");
@@ -524,6 +828,13 @@ int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_str
         return fail(nullptr, NMFKL_E_INVAL, "null index/value pointer");
     if ((int64_t)pr.n * pr.r > ((int64_t)1 << 40) || (int64_t)pr.m * pr.r > ((int64_t)1 << 40))
         return fail(nullptr, NMFKL_E_UNSUPPORTED, "factor too large");
+    if (prm.out_of_core) return create_ooc(pr, prm, hip_stream, out);
+    for (const void* q : {(const void*)pr.csc_ptr, (const void*)pr.csr_ptr, (const void*)pr.W, (const void*)pr.F})
+        if (!is_device_memory(q)) return fail(nullptr, NMFKL_E_INVAL, "V's pointers and W, F must be device memory");
+    if (pr.nnz > 0)
+        for (const void* q : {(const void*)pr.csc_idx, (const void*)pr.csc_val, (const void*)pr.csr_idx,
+                              (const void*)pr.csr_val})
+            if (!is_device_memory(q)) return fail(nullptr, NMFKL_E_INVAL, "V's arrays must be device memory");
 
     nmfkl_handle* h = new (std::nothrow) nmfkl_handle();
     if (!h) return fail(nullptr, NMFKL_E_NOMEM, "host allocation failed");
@@ -688,7 +999,23 @@ int objective_impl(nmfkl_handle* h, double* D_out, bool carried) {
     HIP_TRY(h, launch_finalize_jobs(h->jobtab + kJobSumW, 1, pr.r, h->stream));
     HIP_TRY(h, launch_permute_jobs(h->jobtab + kJobSumF, 1, h->sum_blocks, 0, nullptr, h->stream));
     HIP_TRY(h, launch_finalize_jobs(h->jobtab + kJobSumF, 1, pr.r, h->stream));
-    if (carried && (h->model == kModelCsr || h->model == kModelCsc || h->model == kModelCscFresh)) {
+    if (h->ooc) {
+        // eq. 1 streamed: each column chunk's model values and terms (no model values kept)
+        const int tm = timer_begin(h, NMFKL_T_MODEL);
+        for (size_t c = 0; c < h->chunks[0].size(); ++c) {
+            const auto& ch = h->chunks[0][c];
+            const int b = (int)(c & 1);
+            const int64_t nseg = ch.seg1 - ch.seg0;
+            const int nb = (int)std::min<int64_t>(h->obj_blocks, std::max<int64_t>(1, nseg / 8));
+            HIP_TRY(h, ooc_stage(h, 0, c));
+            HIP_TRY(h, launch_model_objective(h->d_ptr[b], h->d_idx[b], h->d_val[b], (int)nseg, pr.W,
+                                              pr.F + ch.seg0 * pr.r, pr.r, nullptr, h->obj_partials, nb, h->stream));
+            HIP_TRY(h, launch_sum_f64(h->obj_partials, nb, h->d_chunk_obj + c, h->stream));
+            HIP_TRY(h, ooc_release(h, c));
+        }
+        timer_end(h, tm);
+        HIP_TRY(h, launch_sum_f64(h->d_chunk_obj, (int)h->chunks[0].size(), h->dscal, h->stream));
+    } else if (carried && (h->model == kModelCsr || h->model == kModelCsc || h->model == kModelCscFresh)) {
         const bool csr = h->model == kModelCsr;
         const int tm = timer_begin(h, NMFKL_T_TERMS);
         HIP_TRY(h, launch_model_terms(csr ? h->Mcsr : h->Mcsc, csr ? pr.csr_val : pr.csc_val, pr.nnz,
@@ -698,7 +1025,7 @@ int objective_impl(nmfkl_handle* h, double* D_out, bool carried) {
         const int rc = refresh_model(h);
         if (rc) return rc;
     }
-    HIP_TRY(h, launch_sum_f64(h->obj_partials, h->obj_blocks, h->dscal, h->stream));
+    if (!h->ooc) HIP_TRY(h, launch_sum_f64(h->obj_partials, h->obj_blocks, h->dscal, h->stream));
     double part = 0.0;
     std::vector<double> sums(2 * (size_t)pr.r);
     HIP_TRY(h, hipMemcpyAsync(h->host_scal, h->dscal, sizeof(double), hipMemcpyDeviceToHost, h->stream));
@@ -913,6 +1240,7 @@ int nmfkl_batch_create(int32_t nprob, const nmfkl_problem* probs, const nmfkl_pa
     else nmfkl_params_default(&prm);
     std::string why;
     if (check_params(&prm, &why)) return bfail(nullptr, NMFKL_E_INVAL, why);
+    if (prm.out_of_core) return bfail(nullptr, NMFKL_E_UNSUPPORTED, "batches keep V in device memory");
     nmfkl_batch* b = new (std::nothrow) nmfkl_batch();
     if (!b) return bfail(nullptr, NMFKL_E_NOMEM, "host allocation failed");
     b->prm = prm;

@@ -106,6 +106,8 @@ struct SweepArgs {
     float alpha, beta, eps_log, eps_g, eps_x;
     int32_t t_max, j_max, literal_break, guard;
     int32_t tile_bf16;      // 1: Ap holds bfloat16 values (row stride Sp elements)
+    int32_t model_from_tiles;  // 1: each segment computes its model values from the tiles and x
+                               //    (Min unused); Mout may be null (no write-back)
 };
 
 // Fold-in launch arguments (the method parameters travel in a SweepArgs).

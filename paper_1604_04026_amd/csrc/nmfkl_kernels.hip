@@ -619,7 +619,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool 
             const int64_t q = base + l;
             st.id(e) = a.idx[q];
             v = a.val[q];
-            st.ax[e] = a.tile_bf16 ? 0.0 : (a.Mmap ? a.Min[a.Mmap[q]] : a.Min[q]);
+            st.ax[e] = a.model_from_tiles ? 0.0 : (a.Mmap ? a.Min[a.Mmap[q]] : a.Min[q]);
         } else {
             st.id(e) = 0;
             st.ax[e] = 0.0;
@@ -629,10 +629,10 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool 
     if (!active) return;
     const int nchunks = (a.r + CW - 1) / CW;
     float4 cur[E][CW / 4];
-    if (a.tile_bf16) {
-        // Alg. 2's first step on the rounded factor: Ax at the segment's nonzeros from the
-        // tiles and x (float64 sums of exact float32 products), so that the model and the
-        // tiles define one subproblem
+    if (a.model_from_tiles) {
+        // Alg. 2's first step: Ax at the segment's nonzeros from the tiles and x (float64 sums
+        // of exact float32 products), so that the model and the tiles define one subproblem
+        // (bf16-rounded tiles; V streamed from host memory with no model values kept)
         for (int c = 0; c < nchunks; ++c) {
             load_chunk<E, STRIDE, CW>(a, st, L, lo, lane, c, cur);
 #pragma unroll
@@ -684,10 +684,12 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool 
         }
     }
     // write back the model at the nonzeros (this segment order)
+    if (a.Mout) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int l = lo + lane + STRIDE * e;
-        if (l < L) a.Mout[base + l] = st.ax[e];
+        for (int e = 0; e < E; ++e) {
+            const int l = lo + lane + STRIDE * e;
+            if (l < L) a.Mout[base + l] = st.ax[e];
+        }
     }
     if (a.stats && count_stats && lane == 0) {
 #pragma unroll
@@ -1102,7 +1104,7 @@ __global__ void __launch_bounds__(256) k_model_objective(const int64_t* __restri
             const float* wi = W + (int64_t)idx[q] * r;
             double M = 0.0;
             for (int k = 0; k < r; ++k) M = fma((double)wi[k], (double)fj[wv][k], M);
-            Mcsc[q] = M;
+            if (Mcsc) Mcsc[q] = M;
             const float v = val[q];
             if (v != 0.0f) acc += (double)v * log((double)v / M) - (double)v;
         }
