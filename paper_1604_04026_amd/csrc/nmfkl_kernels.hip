@@ -451,40 +451,18 @@ __device__ __forceinline__ float comp(const float4 (&t)[E][CW / 4], int e, int c
     }
 }
 
-// Alg. 2's inner loop for coordinate s = c*CW + cc of one segment.  t holds the chunk's
-// fixed-factor values for the lane's nonzeros, xs the segment's x in LDS (permuted order).
-// LA (lookahead): LS[2k], LS[2k+1] hold eq. 6's sums S1, S2 of chunk coordinate k >= cc at
-// the current model; every trial evaluation also computes the sums of the chunk
-// coordinates after cc at the trial model, so that an accepted step leaves LS valid.  The
-// sums are the same numbers the sequential order would compute later from the same model.
-// Without LA, the coordinate's own sums are evaluated here.
-template <int cc, int E, bool LA, int CW, class Red, class St>
-__device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s,
-                                                const float4 (&t)[E][CW / 4], St& st, float* xs,
-                                                Red& red, float (&LS)[2 * CW], unsigned (&cnt)[6]) {
+// Alg. 2's inner loop for coordinate s of one segment, given the lane's fixed-factor values
+// tk[e] for this coordinate and eq. 6's sums S1, S2 at the current model.  A trial keeps NACC
+// float sums with the coordinate's own S1, S2 at acc[OFF], acc[OFF + 1]; later(e, ww, uu, acc)
+// adds further sums per element (the lookahead form adds those of the chunk's later
+// coordinates) and red.sum(acc, OFF) all-reduces acc[OFF..NACC); commit(acc) runs when a
+// trial is accepted.
+template <int E, int NACC, int OFF, class Later, class Commit, class Red, class St>
+__device__ __forceinline__ void newton_coordinate(const SweepArgs& a, int s, const float (&tk)[E], float S1,
+                                                  float S2, Later&& later, Commit&& commit, St& st, float* xs,
+                                                  Red& red, unsigned (&cnt)[6]) {
     float xk = xs[s];
     const double sA = a.sumA[s];
-    float tk[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) tk[e] = comp<E, CW>(t, e, cc);
-    float S1, S2;
-    if constexpr (LA) {
-        S1 = LS[2 * cc];
-        S2 = LS[2 * cc + 1];
-    } else {
-        float acc[2] = {0.0f, 0.0f};
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            float we, ue;
-            st.wu(e, a.eps_log, we, ue);
-            acc[0] = fmaf(tk[e], we, acc[0]);
-            acc[1] = fmaf(tk[e], tk[e] * ue, acc[1]);
-        }
-        red.sum(acc, 0);
-        S1 = acc[0];
-        S2 = acc[1];
-        cnt[1] += 1;
-    }
     double P = sA + (double)a.alpha * xk + (double)a.beta;
     double g = P - (double)S1;
     float h = S2 + a.alpha;
@@ -502,14 +480,14 @@ __device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s,
         const float dN = d;  // Alg. 2's projected Newton step (the break test uses it)
         double mm[E];
         float wn[E], un[E];
-        float acc[2 * CW];
+        float acc[NACC];
         double gn, Pn;
         float hn;
         int j = 0;
         bool rejected = false;
         for (;;) {
 #pragma unroll
-            for (int i = 0; i < 2 * CW; ++i) acc[i] = 0.0f;
+            for (int i = 0; i < NACC; ++i) acc[i] = 0.0f;
             const double dd = (double)d;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
@@ -520,32 +498,16 @@ __device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s,
                 mm[e] = m;
                 wn[e] = ww;
                 un[e] = uu;
-                acc[2 * cc] = fmaf(tk[e], ww, acc[2 * cc]);
-                acc[2 * cc + 1] = fmaf(tk[e], tk[e] * uu, acc[2 * cc + 1]);
-                if constexpr (LA) {
-#pragma unroll
-                    for (int k = 0; k < CW; ++k) {
-                        if (k > cc) {
-                            const float tq = comp<E, CW>(t, e, k);
-                            acc[2 * k] = fmaf(tq, ww, acc[2 * k]);
-                            acc[2 * k + 1] = fmaf(tq, tq * uu, acc[2 * k + 1]);
-                        }
-                    }
-                }
+                acc[OFF] = fmaf(tk[e], ww, acc[OFF]);
+                acc[OFF + 1] = fmaf(tk[e], tk[e] * uu, acc[OFF + 1]);
+                later(e, ww, uu, acc);
             }
-            if constexpr (LA) {
-                red.sum(acc, 2 * cc);
-            } else {
-                float two[2] = {acc[2 * cc], acc[2 * cc + 1]};
-                red.sum(two, 0);
-                acc[2 * cc] = two[0];
-                acc[2 * cc + 1] = two[1];
-            }
+            red.sum(acc, OFF);
             cnt[1] += 1;
             const float xt = xk + d;
             Pn = sA + (double)a.alpha * xt + (double)a.beta;
-            gn = Pn - (double)acc[2 * cc];
-            hn = acc[2 * cc + 1] + a.alpha;
+            gn = Pn - (double)acc[OFF];
+            hn = acc[OFF + 1] + a.alpha;
             if (!(a.guard && d < 0.0f && g + gn < 0.0)) break;
             if (j == a.j_max) { rejected = true; break; }
             d *= 0.5f;
@@ -558,14 +520,7 @@ __device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s,
             st.ax[e] = mm[e];
             st.set_wu(e, wn[e], un[e]);
         }
-        if constexpr (LA) {
-#pragma unroll
-            for (int k = 0; k < CW; ++k)
-                if (k > cc) {
-                    LS[2 * k] = acc[2 * k];
-                    LS[2 * k + 1] = acc[2 * k + 1];
-                }
-        }
+        commit(acc);
         const float xprev = xk;
         xk = xk + d;
         g = gn;
@@ -578,6 +533,62 @@ __device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s,
         if (steps >= a.t_max) { cnt[5] += 1; break; }
     }
     xs[s] = xk;
+}
+
+// eq. 6's sums of one coordinate at the current model, all-reduced over the segment.
+template <int E, class Red, class St>
+__device__ __forceinline__ void coordinate_sums(const SweepArgs& a, const float (&tk)[E], St& st, Red& red,
+                                                float& S1, float& S2, unsigned (&cnt)[6]) {
+    float acc[2] = {0.0f, 0.0f};
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        float we, ue;
+        st.wu(e, a.eps_log, we, ue);
+        acc[0] = fmaf(tk[e], we, acc[0]);
+        acc[1] = fmaf(tk[e], tk[e] * ue, acc[1]);
+    }
+    red.sum(acc, 0);
+    S1 = acc[0];
+    S2 = acc[1];
+    cnt[1] += 1;
+}
+
+// Coordinate s = c*CW + cc with the chunk's tile values in registers.  LA (lookahead):
+// LS[2k], LS[2k+1] hold eq. 6's sums S1, S2 of chunk coordinate k >= cc at the current model;
+// every trial evaluation also computes the sums of the chunk coordinates after cc at the
+// trial model, so that an accepted step leaves LS valid.  The sums are the same numbers the
+// sequential order would compute later from the same model.  Without LA, the coordinate's
+// own sums are evaluated here.
+template <int cc, int E, bool LA, int CW, class Red, class St>
+__device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s,
+                                                const float4 (&t)[E][CW / 4], St& st, float* xs,
+                                                Red& red, float (&LS)[2 * CW], unsigned (&cnt)[6]) {
+    float tk[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) tk[e] = comp<E, CW>(t, e, cc);
+    if constexpr (LA) {
+        auto later = [&](int e, float ww, float uu, float (&acc)[2 * CW]) {
+#pragma unroll
+            for (int k = cc + 1; k < CW; ++k) {
+                const float tq = comp<E, CW>(t, e, k);
+                acc[2 * k] = fmaf(tq, ww, acc[2 * k]);
+                acc[2 * k + 1] = fmaf(tq, tq * uu, acc[2 * k + 1]);
+            }
+        };
+        auto commit = [&](const float (&acc)[2 * CW]) {
+#pragma unroll
+            for (int k = cc + 1; k < CW; ++k) {
+                LS[2 * k] = acc[2 * k];
+                LS[2 * k + 1] = acc[2 * k + 1];
+            }
+        };
+        newton_coordinate<E, 2 * CW, 2 * cc>(a, s, tk, LS[2 * cc], LS[2 * cc + 1], later, commit, st, xs, red, cnt);
+    } else {
+        float S1, S2;
+        coordinate_sums(a, tk, st, red, S1, S2, cnt);
+        newton_coordinate<E, 2, 0>(a, s, tk, S1, S2, [](int, float, float, float (&)[2]) {},
+                                   [](const float (&)[2]) {}, st, xs, red, cnt);
+    }
 }
 
 // The coordinates of chunk c in order (template recursion: each coordinate index is a
