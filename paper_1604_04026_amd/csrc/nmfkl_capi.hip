@@ -27,7 +27,7 @@ struct BinPlan {
     // the co-residency capacity
     LongWork* long_work = nullptr;  // device: single-block entries, then all rounds
     int single_blocks = 0;
-    struct Round { int first, nblocks, ngroups, pmax; bool huge; };
+    struct Round { int first, nblocks, ngroups, pmax; };
     std::vector<Round> rounds;
     int max_groups = 0, max_pmax = 0;
     // algorithmic (gather-model) bytes and updates of the fused and of the long launches
@@ -72,8 +72,7 @@ struct nmfkl_handle {
     unsigned long long* stats = nullptr;
     unsigned long long* coop_words = nullptr;  // tagged cross-block partial sums of long segments
     unsigned* dev_err = nullptr;       // device-side error flags (bounded waits)
-    int long_capacity = 0;             // co-resident long-segment blocks
-    int huge_capacity = 0;             // ... of the huge-segment kernel
+    int long_capacity = 0;             // co-resident blocks of the cooperative long-segment kernel
     BinPlan binF, binW;
     std::vector<int64_t> hptr_csc, hptr_csr;  // host copies of the segment pointers
     // out-of-core V (params.out_of_core): chunks of whole columns (F-half) / rows (W-half)
@@ -223,8 +222,8 @@ void free_plan(BinPlan* p) {
 // problems are ordered by their first segment, longest first.  Longer segments: B =
 // ceil(L / kLongCapacity) blocks each; those with B = 1 in one ordinary launch, the others
 // packed longest first into cooperative rounds of at most long_capacity blocks.
-int plan_bins(const std::vector<SegSource>& src, int long_capacity, int huge_capacity, int bin_shift,
-              bool problem_major, BinPlan* plan, std::string* err) {
+int plan_bins(const std::vector<SegSource>& src, int long_capacity, int bin_shift, bool problem_major,
+              BinPlan* plan, std::string* err) {
     struct LongSeg { int32_t q, prob; int64_t len; };
     const size_t ns = src.size();
     std::vector<std::vector<std::vector<int32_t>>> groups(kNumVariants, std::vector<std::vector<int32_t>>(ns));
@@ -305,34 +304,27 @@ int plan_bins(const std::vector<SegSource>& src, int long_capacity, int huge_cap
         for (const LongSeg& l : single) lw.push_back(LongWork{l.q, 0, 1, 0, l.prob, 0});
     }
     plan->single_blocks = (int)lw.size();
-    // cooperative rounds: parts of kLongCapacity nonzeros while the segment's blocks fit the
-    // device at once, else parts of kHugeCapacity (the huge kernel, its own rounds)
-    for (int pass = 0; pass < 2; ++pass) {
-        const bool huge = pass == 1;
-        const int cap = huge ? kHugeCapacity : kLongCapacity;
-        const int dev_blocks = huge ? huge_capacity : long_capacity;
-        BinPlan::Round cur{(int)lw.size(), 0, 0, 0, huge};
-        for (const LongSeg& l : longs) {
-            if (l.len <= kLongCapacity) continue;
-            const bool is_huge = (l.len + kLongCapacity - 1) / kLongCapacity > long_capacity;
-            if (is_huge != huge) continue;
-            const int B = (int)((l.len + cap - 1) / cap);
-            if (B > dev_blocks) {
-                *err = "a segment of " + std::to_string(l.len) + " nonzeros needs " + std::to_string(B) +
-                       " co-resident blocks; this device holds " + std::to_string(dev_blocks);
-                return NMFKL_E_UNSUPPORTED;
-            }
-            if (cur.nblocks + B > dev_blocks) {
-                plan->rounds.push_back(cur);
-                cur = BinPlan::Round{(int)lw.size(), 0, 0, 0, huge};
-            }
-            for (int p = 0; p < B; ++p) lw.push_back(LongWork{l.q, p, B, cur.ngroups, l.prob, 0});
-            cur.nblocks += B;
-            cur.ngroups += 1;
-            cur.pmax = std::max(cur.pmax, B);
+    // cooperative rounds: B = ceil(L / kCoopCapacity) blocks per segment, at most the
+    // device's co-resident capacity per round
+    BinPlan::Round cur{(int)lw.size(), 0, 0, 0};
+    for (const LongSeg& l : longs) {
+        if (l.len <= kLongCapacity) continue;
+        const int B = (int)((l.len + kCoopCapacity - 1) / kCoopCapacity);
+        if (B > long_capacity) {
+            *err = "a segment of " + std::to_string(l.len) + " nonzeros needs " + std::to_string(B) +
+                   " co-resident blocks; this device holds " + std::to_string(long_capacity);
+            return NMFKL_E_UNSUPPORTED;
         }
-        if (cur.nblocks > 0) plan->rounds.push_back(cur);
+        if (cur.nblocks + B > long_capacity) {
+            plan->rounds.push_back(cur);
+            cur = BinPlan::Round{(int)lw.size(), 0, 0, 0};
+        }
+        for (int p = 0; p < B; ++p) lw.push_back(LongWork{l.q, p, B, cur.ngroups, l.prob, 0});
+        cur.nblocks += B;
+        cur.ngroups += 1;
+        cur.pmax = std::max(cur.pmax, B);
     }
+    if (cur.nblocks > 0) plan->rounds.push_back(cur);
     for (const auto& r : plan->rounds) {
         plan->max_groups = std::max(plan->max_groups, r.ngroups);
         plan->max_pmax = std::max(plan->max_pmax, r.pmax);
@@ -462,7 +454,7 @@ hipError_t enqueue_plan(const BinPlan& plan, const SweepArgs* tab, unsigned long
     if ((e = launch_sweep_long_single(tab, plan.long_work, plan.single_blocks, s)) != hipSuccess) return e;
     for (const auto& rd : plan.rounds)
         if ((e = launch_sweep_long(tab, plan.long_work + rd.first, rd.nblocks, coop_words, rd.ngroups, dev_err,
-                                   rd.pmax, rd.huge, cooperative, s)) != hipSuccess)
+                                   rd.pmax, cooperative, s)) != hipSuccess)
             return e;
     if (timed) timer_end(timed, tl);
     const int tf = (timed && plan.nblocks) ? timer_begin(timed, fused_kind) : -1;
@@ -736,9 +728,8 @@ int create_ooc(const nmfkl_problem& pr, const nmfkl_params& prm, void* hip_strea
     OOC_HIP(hipMemsetAsync(h->dev_err, 0, sizeof(unsigned), h->stream));
     int ncu = 0;
     OOC_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
-    h->long_capacity = long_kernel_blocks_per_cu(false) * ncu;
-    h->huge_capacity = long_kernel_blocks_per_cu(true) * ncu;
-    if (h->long_capacity <= 0 || h->huge_capacity <= 0) {
+    h->long_capacity = long_kernel_blocks_per_cu() * ncu;
+    if (h->long_capacity <= 0) {
         fail(h, NMFKL_E_DEVICE, "occupancy query of the long-segment kernel failed");
         return bail(NMFKL_E_DEVICE);
     }
@@ -753,8 +744,8 @@ int create_ooc(const nmfkl_problem& pr, const nmfkl_params& prm, void* hip_strea
         for (auto& c : h->chunks[half]) {
             std::vector<int64_t> local(lptr.begin() + c.lptr, lptr.begin() + c.lptr + (c.seg1 - c.seg0) + 1);
             std::string why_plan;
-            const int rc = plan_bins({SegSource{&local, pr.r, 0}}, h->long_capacity, h->huge_capacity, prm.bin_shift,
-                                     false, &c.plan, &why_plan);
+            const int rc = plan_bins({SegSource{&local, pr.r, 0}}, h->long_capacity, prm.bin_shift, false, &c.plan,
+                                     &why_plan);
             if (rc) {
                 fail(h, rc, why_plan);
                 return bail(rc);
@@ -911,9 +902,8 @@ int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_str
     {
         int ncu = 0;
         CREATE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
-        h->long_capacity = long_kernel_blocks_per_cu(false) * ncu;
-        h->huge_capacity = long_kernel_blocks_per_cu(true) * ncu;
-        if (h->long_capacity <= 0 || h->huge_capacity <= 0) {
+        h->long_capacity = long_kernel_blocks_per_cu() * ncu;
+        if (h->long_capacity <= 0) {
             fail(h, NMFKL_E_DEVICE, "occupancy query of the long-segment kernel failed");
             return bail(NMFKL_E_DEVICE);
         }
@@ -922,11 +912,11 @@ int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_str
         CREATE_HIP(hipMemcpy(h->hptr_csc.data(), pr.csc_ptr, h->hptr_csc.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
         CREATE_HIP(hipMemcpy(h->hptr_csr.data(), pr.csr_ptr, h->hptr_csr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
         std::string why_plan;
-        int rc = plan_bins({SegSource{&h->hptr_csc, pr.r, 0}}, h->long_capacity, h->huge_capacity, prm.bin_shift,
-                           false, &h->binF, &why_plan);
+        int rc = plan_bins({SegSource{&h->hptr_csc, pr.r, 0}}, h->long_capacity, prm.bin_shift, false, &h->binF,
+                           &why_plan);
         if (!rc)
-            rc = plan_bins({SegSource{&h->hptr_csr, pr.r, 0}}, h->long_capacity, h->huge_capacity, prm.bin_shift,
-                           false, &h->binW, &why_plan);
+            rc = plan_bins({SegSource{&h->hptr_csr, pr.r, 0}}, h->long_capacity, prm.bin_shift, false, &h->binW,
+                           &why_plan);
         if (rc) {
             fail(h, rc, why_plan);
             return bail(rc);
@@ -1105,7 +1095,7 @@ struct nmfkl_batch {
     size_t coop_words_n = 0;
     unsigned* dev_err = nullptr;
     int64_t* t_dev = nullptr;
-    int long_capacity = 0, huge_capacity = 0;
+    int long_capacity = 0;
     int graph_coop = -1;
     std::vector<std::pair<int, hipGraphExec_t>> graphs;
     std::string err;
@@ -1159,8 +1149,8 @@ int batch_plan(nmfkl_batch* b) {
     }
     std::string why;
     const bool pm = (b->prm.tuning & 2) != 0;
-    int rc = plan_bins(srcF, b->long_capacity, b->huge_capacity, b->prm.bin_shift, pm, &b->plan[0], &why);
-    if (!rc) rc = plan_bins(srcW, b->long_capacity, b->huge_capacity, b->prm.bin_shift, pm, &b->plan[1], &why);
+    int rc = plan_bins(srcF, b->long_capacity, b->prm.bin_shift, pm, &b->plan[0], &why);
+    if (!rc) rc = plan_bins(srcW, b->long_capacity, b->prm.bin_shift, pm, &b->plan[1], &why);
     if (rc) return bfail(b, rc, why);
     const int groups = std::max(std::max(b->plan[0].max_groups, b->plan[1].max_groups), 1);
     const int pmax = std::max(std::max(b->plan[0].max_pmax, b->plan[1].max_pmax), 1);
@@ -1263,7 +1253,6 @@ int nmfkl_batch_create(int32_t nprob, const nmfkl_problem* probs, const nmfkl_pa
         b->hs.push_back(h);
     }
     b->long_capacity = b->hs[0]->long_capacity;
-    b->huge_capacity = b->hs[0]->huge_capacity;
     std::vector<SweepArgs> args(2 * (size_t)nprob);
     std::vector<PermJob> jobs(2 * (size_t)nprob);
     for (int half = 0; half < 2; ++half) {

@@ -153,10 +153,11 @@ constexpr int kMaxFusedLength = 1024;   // 256 * 4
 constexpr int kLongThreads = 256;
 constexpr int kLongE = 8;
 constexpr int kLongCapacity = kLongThreads * kLongE;
-// Segments too long for the co-resident capacity at kLongCapacity per block: kHugeE nonzeros
-// per thread (fewer blocks per compute unit, twice the nonzeros per block).
-constexpr int kHugeE = 16;
-constexpr int kHugeCapacity = kLongThreads * kHugeE;
+// Segments longer than kLongCapacity: blocks of kCoopE nonzeros per thread (two blocks per
+// compute unit; more nonzeros per unit than three blocks of kLongE, so fewer cooperative
+// rounds), B = ceil(L / kCoopCapacity) of them per segment.
+constexpr int kCoopE = 20;
+constexpr int kCoopCapacity = kLongThreads * kCoopE;
 
 // A block of a long-segment launch.
 struct LongWork {
@@ -190,12 +191,10 @@ constexpr int kCoopValues = 2 * kChunk;
 // (2 * pmax * kCoopValues words per group, pmax = largest B in the launch).
 // cooperative = false: ordinary launch of the same grid (inside a captured graph), which
 // relies on the grid fitting the device's co-resident capacity; the waits stay bounded.
-// huge: the kHugeE kernel (parts of kHugeCapacity nonzeros), else parts of kLongCapacity.
 hipError_t launch_sweep_long(const SweepArgs* tab, const LongWork* work, int nblocks, unsigned long long* words,
-                             int ngroups, unsigned* err, int pmax, bool huge, bool cooperative,
-                             hipStream_t stream);
-// Co-resident blocks of the long-segment kernel per compute unit (0 on failure).
-int long_kernel_blocks_per_cu(bool huge);
+                             int ngroups, unsigned* err, int pmax, bool cooperative, hipStream_t stream);
+// Co-resident blocks of the cooperative long-segment kernel per compute unit (0 on failure).
+int long_kernel_blocks_per_cu();
 hipError_t launch_model_objective(const int64_t* csc_ptr, const int32_t* csc_idx,
                                   const float* csc_val, int m, const float* W, const float* F, int r,
                                   double* Mcsc, double* partials, int nblocks, hipStream_t stream);

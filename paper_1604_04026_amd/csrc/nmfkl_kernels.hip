@@ -778,9 +778,10 @@ hipError_t launch_sweep_fused(const SweepArgs* tab, const BlockWork* work, const
 // per segment (B = 1), ordinary launch.  COOP = true: the blocks of a segment cooperate
 // through CoopReducer; all blocks of the launch are co-resident (cooperative launch), so
 // every wait ends.  Counts and ids live in LDS, the model values in registers, w and u are
-// recomputed from the model at each chunk start, and tile chunks are 4 coordinates wide:
-// this keeps the kernel within 168 registers without spills, so 3 blocks share a compute
-// unit and a cooperative launch holds 1.5 times the nonzeros it would at 2.
+// recomputed from the model at each chunk start, and tile chunks are 4 coordinates wide.
+// Single-block segments (COOP = false) use kLongE = 8 nonzeros per thread within 168
+// registers (3 blocks per compute unit); cooperative segments use kCoopE = 20 (2 blocks per
+// compute unit, 10240 nonzeros per unit: fewer rounds than 3 blocks of 2048).
 constexpr int kLongCW = 4;
 
 template <bool COOP, int E>
@@ -843,33 +844,27 @@ hipError_t launch_sweep_long_single(const SweepArgs* tab, const LongWork* work, 
 }
 
 hipError_t launch_sweep_long(const SweepArgs* tab, const LongWork* work, int nblocks, unsigned long long* words,
-                             int ngroups, unsigned* err, int pmax, bool huge, bool cooperative,
-                             hipStream_t stream) {
+                             int ngroups, unsigned* err, int pmax, bool cooperative, hipStream_t stream) {
     if (nblocks <= 0) return hipSuccess;
     const int64_t nwords = (int64_t)ngroups * 2 * pmax * kCoopValues;
     hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((nwords + 255) / 256)), dim3(256), 0, stream, words, nwords);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const void* fn = huge ? reinterpret_cast<const void*>(k_sweep_long<true, kHugeE>)
-                          : reinterpret_cast<const void*>(k_sweep_long<true, kLongE>);
     if (!cooperative) {
-        if (huge)
-            hipLaunchKernelGGL((k_sweep_long<true, kHugeE>), dim3(nblocks), dim3(kLongThreads), 0, stream, tab,
-                               work, words, err, pmax);
-        else
-            hipLaunchKernelGGL((k_sweep_long<true, kLongE>), dim3(nblocks), dim3(kLongThreads), 0, stream, tab,
-                               work, words, err, pmax);
+        hipLaunchKernelGGL((k_sweep_long<true, kCoopE>), dim3(nblocks), dim3(kLongThreads), 0, stream, tab, work,
+                           words, err, pmax);
         return hipGetLastError();
     }
     void* args[] = {&tab, &work, &words, &err, &pmax};
-    return hipLaunchCooperativeKernel(fn, dim3(nblocks), dim3(kLongThreads), args, 0, stream);
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_sweep_long<true, kCoopE>), dim3(nblocks),
+                                      dim3(kLongThreads), args, 0, stream);
 }
 
-int long_kernel_blocks_per_cu(bool huge) {
+int long_kernel_blocks_per_cu() {
     int nb = 0;
-    const void* fn = huge ? reinterpret_cast<const void*>(k_sweep_long<true, kHugeE>)
-                          : reinterpret_cast<const void*>(k_sweep_long<true, kLongE>);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kLongThreads, 0) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_sweep_long<true, kCoopE>),
+                                                     kLongThreads, 0) != hipSuccess)
+        return 0;
     return nb;
 }
 

@@ -389,7 +389,7 @@ def huge_row_problem(m=1_700_000, r=4, seed=0):
     return workloads._problem(3, m, r, ptr, rows.astype(np.int32), val, seed, 11, {"name": "huge row"})
 
 
-def test_huge_row_uses_the_wide_kernel_and_matches_the_oracle():
+def test_huge_row_matches_the_oracle():
     prob = huge_row_problem()
     assert np.diff(prob.csr_ptr).max() > 768 * 2048
     t = 0
