@@ -259,7 +259,7 @@ def serving_leg(P, W, arrivals, ptr, idx, val, window_s, log):
     log(f"[bench] serving: plain {plain_out}")
     P.nmfkl_model_destroy(m)
     return {
-        "workload": f"fold-in: W 50000x{r} Gamma(0.1) resident; {N} Poisson requests at 20000/s, "
+        "workload": f"fold-in: W 50000x{r} Gamma(0.1) resident; {N} Poisson requests at {N / arrivals[-1]:.0f}/s, "
                     "lengths LogNormal(ln 80, 1) in [1, 5000], Zipf(1.1) words, 1+Geometric(0.6) counts; "
                     "relative KL tolerance 1e-5",
         "server": srv_out, "plain_per_request": plain_out,
@@ -516,6 +516,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=100_000)
+    ap.add_argument("--serving-rate", type=float, default=20_000.0, help="offered fold-in requests per second")
     ap.add_argument("--plain-window", type=float, default=3.0, help="seconds of per-request plain fold-in")
     ap.add_argument("--workers", type=int, default=16, help="processes generating the batched problems")
     ap.add_argument("--tuning", type=int, default=0, help="nmfkl_params.tuning bits (result-neutral)")
@@ -565,7 +566,8 @@ def main():
     if not args.no_serving:
         t0 = time.perf_counter()
         W = workloads.serving_model(seed=args.seed)
-        arrivals, sptr, sidx, sval = workloads.serving_requests(args.serving_requests, seed=args.seed)
+        arrivals, sptr, sidx, sval = workloads.serving_requests(args.serving_requests, rate=args.serving_rate,
+                                                                 seed=args.seed)
         serving = (W, arrivals, sptr, sidx, sval)
         log(f"[bench] {args.serving_requests} serving requests generated ({time.perf_counter() - t0:.1f} s)")
 
