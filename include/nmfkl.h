@@ -24,6 +24,9 @@
  *    it in the matching destroy call.  Host pointers are read during the call only.
  *  - All device work is enqueued on the caller's HIP stream (passed as void*; NULL means
  *    the default stream).  Only functions that return host values synchronise that stream.
+ *    An out-of-core handle also copies V chunks on an internal stream ordered against the
+ *    caller's stream with events; a batch captures its graph on a private stream and
+ *    replays it on the caller's stream; the fold-in server runs its lanes on streams it owns.
  *    Device-side failures surface at the next synchronising call.
  *  - Precision: values, factors and the derivative sums are float32; the model values at
  *    the nonzeros (W_i . F_j, kept between halves), the factor column sums and the
