@@ -56,6 +56,8 @@ struct nmfkl_handle {
     int Sp = 0;
     // scratch
     float* Ap = nullptr;          // permuted padded copy of the fixed factor
+    float* Apc = nullptr;         // its chunk-major copy (halves with long segments only)
+    bool long_half[2] = {false, false};  // the F-half / W-half has segments for the long kernels
     double* sumA = nullptr;       // its column sums (permuted order)
     double* partials = nullptr;   // per-block column-sum partials
     int sum_blocks = 0;
@@ -179,7 +181,7 @@ void release(nmfkl_handle* h) {
     for (hipEvent_t ev : h->event_pool) (void)hipEventDestroy(ev);
     h->event_pool.clear();
     auto f = [](void* p) { if (p) (void)hipFree(p); };
-    f(h->Ap); f(h->sumA); f(h->partials); f(h->ids); f(h->Mcsc); f(h->Mcsr);
+    f(h->Ap); f(h->Apc); f(h->sumA); f(h->partials); f(h->ids); f(h->Mcsc); f(h->Mcsr);
     f(h->csc2csr); f(h->csr2csc); f(h->obj_partials); f(h->sums2); f(h->dscal); f(h->stats);
     f(h->binF.work); f(h->binF.segs); f(h->binW.work); f(h->binW.segs);
     f(h->binF.long_work); f(h->binW.long_work);
@@ -381,6 +383,8 @@ SweepArgs sweep_args(nmfkl_handle* h, bool fhalf) {
     a.guard = h->prm.guard;
     a.tile_bf16 = h->prm.tile_bf16;
     a.model_from_tiles = h->prm.tile_bf16 || h->prm.out_of_core;
+    a.Apc = h->long_half[fhalf ? 0 : 1] ? h->Apc : nullptr;
+    a.Prows = fhalf ? pr.n : pr.m;
     return a;
 }
 
@@ -418,6 +422,7 @@ void make_jobs(nmfkl_handle* h, PermJob (&jobs)[kNumJobs]) {
         j.first_sum = 0;
         if (k == kJobF || k == kJobW) {
             j.Ap = h->Ap;
+            j.Apc = h->long_half[k == kJobF ? 0 : 1] ? h->Apc : nullptr;
             j.sums = h->sumA;
             j.ids = h->ids;
             j.identity = 0;
@@ -752,7 +757,9 @@ int create_ooc(const nmfkl_problem& pr, const nmfkl_params& prm, void* hip_strea
             }
             groups = std::max(groups, c.plan.max_groups);
             pmax = std::max(pmax, c.plan.max_pmax);
+            if (c.plan.single_blocks > 0 || !c.plan.rounds.empty()) h->long_half[half] = true;
         }
+    if (h->long_half[0] || h->long_half[1]) OOC_HIP(dalloc(&h->Apc, (size_t)Pmax * ((pr.r + 3) & ~3)));
     OOC_HIP(dalloc(&h->coop_words, (size_t)groups * 2 * pmax * kCoopValues));
     OOC_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->h_lptr), lptr.size() * sizeof(int64_t), hipHostMallocDefault));
     std::memcpy(h->h_lptr, lptr.data(), lptr.size() * sizeof(int64_t));
@@ -921,6 +928,10 @@ int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_str
             fail(h, rc, why_plan);
             return bail(rc);
         }
+        h->long_half[0] = h->binF.single_blocks > 0 || !h->binF.rounds.empty();
+        h->long_half[1] = h->binW.single_blocks > 0 || !h->binW.rounds.empty();
+        if (h->long_half[0] || h->long_half[1])
+            CREATE_HIP(dalloc(&h->Apc, (size_t)Pmax * ((pr.r + 3) & ~3)));
         const int groups = std::max(h->binF.max_groups, h->binW.max_groups);
         const int pmax = std::max(h->binF.max_pmax, h->binW.max_pmax);
         // k_sweep_long<true> addresses words + group * (2 * pmax * kCoopValues) + ...

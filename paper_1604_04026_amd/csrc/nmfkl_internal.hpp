@@ -85,6 +85,9 @@ struct PermJob {
     int32_t bf16;         // 1: the copy holds bfloat16 values (round to nearest even) and the
                           //    column sums are those of the rounded values
     int32_t pad;
+    float* Apc;           // nullptr, or a second copy in chunk-major order: the values of permuted
+                          // columns 4c..4c+3 of row p at Apc[(c * P + p) * 4 ..] (zero beyond r;
+                          // bfloat16 when bf16)
 };
 
 // One half-sweep's per-launch arguments (kernels read them from a device table).
@@ -108,6 +111,9 @@ struct SweepArgs {
     int32_t tile_bf16;      // 1: Ap holds bfloat16 values (row stride Sp elements)
     int32_t model_from_tiles;  // 1: each segment computes its model values from the tiles and x
                                //    (Min unused); Mout may be null (no write-back)
+    const float* Apc;       // nullptr, or the chunk-major copy (PermJob::Apc) read by the
+                            // long-segment kernels
+    int64_t Prows;          // rows of the fixed factor (the chunk stride of Apc)
 };
 
 // Fold-in launch arguments (the method parameters travel in a SweepArgs).

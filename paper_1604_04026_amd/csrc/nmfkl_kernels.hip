@@ -110,7 +110,7 @@ __device__ void job_order(const PermJob& jb, int64_t t, int32_t* sid, uint64_t* 
 
 // Block b of job j covers rows [lb*rpb, (lb+1)*rpb), lb = b - first_block.  Thread (ry, cx)
 // walks rows ry, ry+4, ... for permuted column s = s0 + cx, reading A[p][ids[s]] and
-// writing Ap[p][s] (zero in the padding).  Per-block float64 partial sums go to
+// writing Ap[p][s] (zero in the padding), and the chunk-major copy when the job has one.  Per-block float64 partial sums go to
 // partials[lb*r + s]; k_finalize_jobs adds them in a fixed order, so the result is
 // deterministic.  The job's first block also stores the order for the sweep kernels.
 __global__ void __launch_bounds__(256) k_permute_jobs(const PermJob* __restrict__ jobs, int njobs,
@@ -123,7 +123,7 @@ __global__ void __launch_bounds__(256) k_permute_jobs(const PermJob* __restrict_
     const int64_t lb = (int64_t)blockIdx.x - jb.first_block;
     const int64_t t = t_arg + (t_dev ? *t_dev : 0);
     job_order(jb, t, sid, words);
-    const int r = jb.r, Sp = jb.Sp;
+    const int r = jb.r, Sp = jb.Sp, Sc = (r + 3) & ~3;
     if (jb.ids && lb == 0)
         for (int s = threadIdx.x; s < r; s += 256) jb.ids[s] = sid[s];
     const int cx = threadIdx.x & 63, ry = threadIdx.x >> 6;
@@ -136,12 +136,15 @@ __global__ void __launch_bounds__(256) k_permute_jobs(const PermJob* __restrict_
         if (s < Sp) {
             for (int64_t p = p0 + ry; p < p1; p += 4) {
                 float a = k >= 0 ? jb.A[p * r + k] : 0.0f;
+                const int64_t pc = ((int64_t)(s >> 2) * jb.P + p) * 4 + (s & 3);
                 if (jb.bf16) {
                     const uint16_t q = bf16_rne(a);
                     a = bf16_to_float(q);
                     if (jb.Ap) reinterpret_cast<uint16_t*>(jb.Ap)[p * Sp + s] = q;
-                } else if (jb.Ap) {
-                    jb.Ap[p * Sp + s] = a;
+                    if (jb.Apc && s < Sc) reinterpret_cast<uint16_t*>(jb.Apc)[pc] = q;
+                } else {
+                    if (jb.Ap) jb.Ap[p * Sp + s] = a;
+                    if (jb.Apc && s < Sc) jb.Apc[pc] = a;
                 }
                 acc += (double)a;
             }
@@ -404,17 +407,33 @@ struct CoopReducer {
 };
 
 // Elements handled by this lane: l = lo + lane + STRIDE * e, e < E, restricted to l < L.
-// A tile chunk holds CW consecutive permuted coordinates (CW / 4 float4 per nonzero).
+// A tile chunk holds CW consecutive permuted coordinates (CW = 2: the first two components
+// of one float4 per nonzero; CW a multiple of 4: CW / 4 float4 per nonzero).  Chunks of 4
+// come from the chunk-major copy when there is one: the 16 bytes of every row for chunk c
+// then lie in one compact slice, which stays in L2 while the blocks of a long-segment launch
+// work through chunk c, where rows of the row-major copy are evicted between chunks.
+template <int CW>
+constexpr int kQuads = (CW + 3) / 4;
+
 template <int E, int STRIDE, int CW, class St>
 __device__ __forceinline__ void load_chunk(const SweepArgs& a, St& st, int L, int lo,
-                                           int lane, int c, float4 (&t)[E][CW / 4]) {
+                                           int lane, int c, float4 (&t)[E][kQuads<CW>]) {
+    // (row p, chunk c) starts at element p * rs + c * cs of the copy (uniform strides)
+    const bool cm = CW == 4 && a.Apc != nullptr;
+    const float* base = cm ? a.Apc : a.Ap;
+    const int64_t cs = cm ? a.Prows * 4 : (int64_t)CW;
+    const int64_t rs = cm ? 4 : (int64_t)a.Sp;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         if (lo + lane + STRIDE * e < L) {
+            const int64_t off = (int64_t)st.id(e) * rs + c * cs;
             if (a.tile_bf16) {
-                // CW bfloat16 values: CW / 8 16-byte loads (CW = 4: one 8-byte load)
-                const uint16_t* p = reinterpret_cast<const uint16_t*>(a.Ap) + (int64_t)st.id(e) * a.Sp + c * CW;
-                if constexpr (CW == 4) {
+                // CW bfloat16 values: one 4- or 8-byte load (CW = 2, 4) or CW / 8 16-byte loads
+                const uint16_t* p = reinterpret_cast<const uint16_t*>(base) + off;
+                if constexpr (CW == 2) {
+                    const unsigned w = *reinterpret_cast<const unsigned*>(p);
+                    t[e][0] = make_float4(__uint_as_float(w << 16), __uint_as_float(w & 0xFFFF0000u), 0.f, 0.f);
+                } else if constexpr (CW == 4) {
                     const uint2 w = *reinterpret_cast<const uint2*>(p);
                     t[e][0] = make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xFFFF0000u),
                                           __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xFFFF0000u));
@@ -428,20 +447,23 @@ __device__ __forceinline__ void load_chunk(const SweepArgs& a, St& st, int L, in
                                                       __uint_as_float(w.w << 16), __uint_as_float(w.w & 0xFFFF0000u));
                     }
                 }
+            } else if constexpr (CW == 2) {
+                const float2 w = *reinterpret_cast<const float2*>(base + off);
+                t[e][0] = make_float4(w.x, w.y, 0.f, 0.f);
             } else {
-                const float4* p = reinterpret_cast<const float4*>(a.Ap + (int64_t)st.id(e) * a.Sp + c * CW);
+                const float4* p = reinterpret_cast<const float4*>(base + off);
 #pragma unroll
                 for (int q = 0; q < CW / 4; ++q) t[e][q] = p[q];
             }
         } else {
 #pragma unroll
-            for (int q = 0; q < CW / 4; ++q) t[e][q] = make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int q = 0; q < kQuads<CW>; ++q) t[e][q] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
     }
 }
 
 template <int E, int CW>
-__device__ __forceinline__ float comp(const float4 (&t)[E][CW / 4], int e, int cc) {
+__device__ __forceinline__ float comp(const float4 (&t)[E][kQuads<CW>], int e, int cc) {
     const float4 q = t[e][cc >> 2];
     switch (cc & 3) {
         case 0: return q.x;
@@ -561,7 +583,7 @@ __device__ __forceinline__ void coordinate_sums(const SweepArgs& a, const float 
 // own sums are evaluated here.
 template <int cc, int E, bool LA, int CW, class Red, class St>
 __device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s,
-                                                const float4 (&t)[E][CW / 4], St& st, float* xs,
+                                                const float4 (&t)[E][kQuads<CW>], St& st, float* xs,
                                                 Red& red, float (&LS)[2 * CW], unsigned (&cnt)[6]) {
     float tk[E];
 #pragma unroll
@@ -596,7 +618,7 @@ __device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s,
 // cmap (fold-in): x and sumA are kept in the original coordinate order and step s of the
 // pass visits coordinate cmap[s]; null: they are already in the sweep's order.
 template <int CC, int E, bool LA, int CW, class Red, class St>
-__device__ __forceinline__ void chunk_steps(const SweepArgs& a, int c, const float4 (&t)[E][CW / 4],
+__device__ __forceinline__ void chunk_steps(const SweepArgs& a, int c, const float4 (&t)[E][kQuads<CW>],
                                             St& st, float* xs, Red& red, float (&LS)[2 * CW],
                                             unsigned (&cnt)[6], const int32_t* cmap = nullptr) {
     if constexpr (CC < CW) {
@@ -639,7 +661,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool 
     }
     if (!active) return;
     const int nchunks = (a.r + CW - 1) / CW;
-    float4 cur[E][CW / 4];
+    float4 cur[E][kQuads<CW>];
     if (a.model_from_tiles) {
         // Alg. 2's first step: Ax at the segment's nonzeros from the tiles and x (float64 sums
         // of exact float32 products), so that the model and the tiles define one subproblem
@@ -663,7 +685,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool 
     unsigned cnt[6] = {0, 0, 0, 0, 0, 0};
     load_chunk<E, STRIDE, CW>(a, st, L, lo, lane, 0, cur);
     for (int c = 0; c < nchunks; ++c) {
-        float4 nxt[E][CW / 4];
+        float4 nxt[E][kQuads<CW>];
         if (PREFETCH && c + 1 < nchunks) load_chunk<E, STRIDE, CW>(a, st, L, lo, lane, c + 1, nxt);
         float LS[2 * CW];
         if constexpr (LA) {
@@ -689,7 +711,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool 
 #pragma unroll
             for (int e = 0; e < E; ++e)
 #pragma unroll
-                for (int q = 0; q < CW / 4; ++q) cur[e][q] = nxt[e][q];
+                for (int q = 0; q < kQuads<CW>; ++q) cur[e][q] = nxt[e][q];
         } else if (c + 1 < nchunks) {
             load_chunk<E, STRIDE, CW>(a, st, L, lo, lane, c + 1, cur);
         }
@@ -783,6 +805,7 @@ hipError_t launch_sweep_fused(const SweepArgs* tab, const BlockWork* work, const
 // registers (3 blocks per compute unit); cooperative segments use kCoopE = 20 (2 blocks per
 // compute unit, 10240 nonzeros per unit: fewer rounds than 3 blocks of 2048).
 constexpr int kLongCW = 4;
+constexpr int kCoopCW = 4;
 
 template <bool COOP, int E>
 __global__ void __launch_bounds__(kLongThreads, E <= kLongE ? 3 : 2)
@@ -819,7 +842,7 @@ k_sweep_long(const SweepArgs* __restrict__ tab, const LongWork* __restrict__ wor
         red.B = wk.B;
         red.part = wk.part;
         red.round = 0;
-        sweep_segment<kLongThreads, false, true, kLongCW>(a, wk.seg, true, lane, wk.part * CAP,
+        sweep_segment<kLongThreads, false, true, kCoopCW>(a, wk.seg, true, lane, wk.part * CAP,
                                                           wk.part == 0, xs, red, st);
     } else {
         BlockReducer<kLongThreads> red{red_lds, 0, nullptr};
