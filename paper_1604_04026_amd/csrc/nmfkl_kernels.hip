@@ -39,18 +39,35 @@ __device__ __forceinline__ float dpp_mirror(float v) {
     return __builtin_amdgcn_update_dpp(0.0f, v, 0x140, 0xF, 0xF, false);  // row_mirror
 }
 
+// Sum of the lane's value and that of lane ^ 16 (ROWS = 16) or lane ^ 32 (ROWS = 32): the
+// gfx950 row-swap permutes exchange whole 16-lane rows (odd rows of the first operand with
+// even rows of the second; the upper half of the first with the lower half of the second),
+// so adding the two results gives both partners the same sum, in registers only.
+template <int ROWS>
+__device__ __forceinline__ float row_swap_sum(float v) {
+    const unsigned u = __float_as_uint(v);
+    if constexpr (ROWS == 16) {
+        const auto p = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+        return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+    } else {
+        const auto p = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+        return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+    }
+}
+
 // All-reduce over aligned groups of G lanes (G a power of two, G <= 64).  After the two quad
 // steps every lane holds its quad's sum; the half-row mirror pairs quad q with the other quad
-// of its 8-lane half, the row mirror pairs the two halves of a 16-lane row.  Each step adds
-// the same two partial sums on both partners, so all lanes of a group end bit-identical.
+// of its 8-lane half, the row mirror pairs the two halves of a 16-lane row, and the row swaps
+// pair rows.  Each step adds the same two partial sums on both partners, so all lanes of a
+// group end bit-identical.
 template <int G>
 __device__ __forceinline__ float group_sum(float v) {
     if constexpr (G >= 2) v += dpp_quad_xor1(v);
     if constexpr (G >= 4) v += dpp_quad_xor2(v);
     if constexpr (G >= 8) v += dpp_half_mirror(v);
     if constexpr (G >= 16) v += dpp_mirror(v);
-    if constexpr (G >= 32) v += __shfl_xor(v, 16);
-    if constexpr (G >= 64) v += __shfl_xor(v, 32);
+    if constexpr (G >= 32) v = row_swap_sum<16>(v);
+    if constexpr (G >= 64) v = row_swap_sum<32>(v);
     return v;
 }
 
@@ -136,15 +153,12 @@ __global__ void __launch_bounds__(256) k_permute_jobs(const PermJob* __restrict_
         if (s < Sp) {
             for (int64_t p = p0 + ry; p < p1; p += 4) {
                 float a = k >= 0 ? jb.A[p * r + k] : 0.0f;
-                const int64_t pc = ((int64_t)(s >> 2) * jb.P + p) * 4 + (s & 3);
                 if (jb.bf16) {
                     const uint16_t q = bf16_rne(a);
                     a = bf16_to_float(q);
                     if (jb.Ap) reinterpret_cast<uint16_t*>(jb.Ap)[p * Sp + s] = q;
-                    if (jb.Apc && s < Sc) reinterpret_cast<uint16_t*>(jb.Apc)[pc] = q;
-                } else {
-                    if (jb.Ap) jb.Ap[p * Sp + s] = a;
-                    if (jb.Apc && s < Sc) jb.Apc[pc] = a;
+                } else if (jb.Ap) {
+                    jb.Ap[p * Sp + s] = a;
                 }
                 acc += (double)a;
             }
@@ -154,6 +168,20 @@ __global__ void __launch_bounds__(256) k_permute_jobs(const PermJob* __restrict_
         if (ry == 0 && s < r)
             jb.partials[lb * r + s] = ((red[0][cx] + red[1][cx]) + red[2][cx]) + red[3][cx];
         __syncthreads();
+    }
+    if (jb.Apc) {
+        // the chunk-major copy: thread (row group, component q) writes 16 consecutive rows'
+        // 16-byte chunk entries per wave, so the stores are contiguous
+        const int q = threadIdx.x & 3;
+        for (int c = 0; c < Sc / 4; ++c) {
+            const int k = sid[4 * c + q];
+            for (int64_t p = p0 + (threadIdx.x >> 2); p < p1; p += 64) {
+                const float a = k >= 0 ? jb.A[p * r + k] : 0.0f;
+                const int64_t pc = ((int64_t)c * jb.P + p) * 4 + q;
+                if (jb.bf16) reinterpret_cast<uint16_t*>(jb.Apc)[pc] = bf16_rne(a);
+                else jb.Apc[pc] = a;
+            }
+        }
     }
 }
 
