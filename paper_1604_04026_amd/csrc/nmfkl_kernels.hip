@@ -762,7 +762,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool 
 // latency is exposed without prefetching).
 constexpr int kFusedCW = 8;
 
-template <int G, int E, bool LA>
+template <int G, int E, bool LA, int CW = kFusedCW>
 __device__ __forceinline__ void sweep_block(const SweepArgs& ag, const BlockWork& wk, const int32_t* segs,
                                             float* xs_all, float* red_lds, double* sA_lds) {
     const int slot = threadIdx.x / G;
@@ -781,10 +781,40 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& ag, const BlockWork
     RegElems<E> st;
     if constexpr (G <= 64) {
         WaveReducer<G> red;
-        sweep_segment<G, false, LA, kFusedCW>(a, seg, active, lane, 0, true, xs, red, st);
+        sweep_segment<G, false, LA, CW>(a, seg, active, lane, 0, true, xs, red, st);
     } else {
         BlockReducer<G> red{red_lds, 0, nullptr};
-        sweep_segment<G, false, LA, kFusedCW>(a, seg, active, lane, 0, true, xs, red, st);
+        sweep_segment<G, false, LA, CW>(a, seg, active, lane, 0, true, xs, red, st);
+        __syncthreads();
+    }
+    if (active)
+        for (int s = lane; s < a.r; s += G) a.X[(int64_t)seg * a.r + a.ids[s]] = xs[s];
+}
+
+template <int G, int E, int CW>
+__device__ __forceinline__ void sweep_block_lds(const SweepArgs& ag, const BlockWork& wk, const int32_t* segs,
+                                                float* xs_all, double* sA_lds, int32_t* s_id, float* s_v,
+                                                float* red_lds) {
+    const int slot = threadIdx.x / G;
+    const int lane = threadIdx.x % G;
+    const bool active = slot < wk.count;
+    const int seg = active ? segs[wk.first + slot] : 0;
+    float* xs = xs_all + slot * NMFKL_R_MAX;
+    if (active)
+        for (int s = lane; s < ag.r; s += G) xs[s] = ag.X[(int64_t)seg * ag.r + ag.ids[s]];
+    for (int s = threadIdx.x; s < ag.r; s += kFusedThreads) sA_lds[s] = ag.sumA[s];
+    SweepArgs a = ag;
+    a.sumA = sA_lds;
+    __syncthreads();
+    LdsElemsNoWU<E, G> st;
+    st.idp = s_id + slot * G * E + lane;
+    st.vp = s_v + slot * G * E + lane;
+    if constexpr (G <= 64) {
+        WaveReducer<G> red;
+        sweep_segment<G, false, true, CW>(a, seg, active, lane, 0, true, xs, red, st);
+    } else {
+        BlockReducer<G> red{red_lds, 0, nullptr};
+        sweep_segment<G, false, true, CW>(a, seg, active, lane, 0, true, xs, red, st);
         __syncthreads();
     }
     if (active)
@@ -802,6 +832,8 @@ k_sweep_fused(const SweepArgs* __restrict__ tab, const BlockWork* __restrict__ w
     __shared__ float xs_all[(kFusedThreads / 8) * NMFKL_R_MAX];
     __shared__ float red[2 * (kFusedThreads / 64) * kMaxRed];
     __shared__ double sA_lds[NMFKL_R_MAX];
+    __shared__ int32_t s_id[kFusedThreads * 8];
+    __shared__ float s_v[kFusedThreads * 8];
     const BlockWork wk = work[blockIdx.x];
     const SweepArgs a = tab[wk.prob];
     switch (wk.variant) {
@@ -809,6 +841,7 @@ k_sweep_fused(const SweepArgs* __restrict__ tab, const BlockWork* __restrict__ w
         case 1: sweep_block<16, 4, false>(a, wk, segs, xs_all, red, sA_lds); break;
         case 2: sweep_block<32, 4, false>(a, wk, segs, xs_all, red, sA_lds); break;
         case 3: sweep_block<64, 4, false>(a, wk, segs, xs_all, red, sA_lds); break;
+        case 4: sweep_block_lds<64, 8, 4>(a, wk, segs, xs_all, sA_lds, s_id, s_v, red); break;
         default: sweep_block<256, 4, LA256>(a, wk, segs, xs_all, red, sA_lds); break;
     }
 }
