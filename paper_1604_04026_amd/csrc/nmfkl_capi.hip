@@ -75,6 +75,7 @@ struct nmfkl_handle {
     unsigned long long* coop_words = nullptr;  // tagged cross-block partial sums of long segments
     unsigned* dev_err = nullptr;       // device-side error flags (bounded waits)
     int long_capacity = 0;             // co-resident blocks of the cooperative long-segment kernel
+    int single_capacity = 0;           // co-resident blocks of the single-block long-segment kernel
     BinPlan binF, binW;
     std::vector<int64_t> hptr_csc, hptr_csr;  // host copies of the segment pointers
     // out-of-core V (params.out_of_core): chunks of whole columns (F-half) / rows (W-half)
@@ -223,9 +224,10 @@ void free_plan(BinPlan* p) {
 // cut into blocks of kFusedThreads / G segments of that problem, and the blocks of all
 // problems are ordered by their first segment, longest first.  Longer segments: B =
 // ceil(L / kLongCapacity) blocks each; those with B = 1 in one ordinary launch, the others
-// packed longest first into cooperative rounds of at most long_capacity blocks.
-int plan_bins(const std::vector<SegSource>& src, int long_capacity, int bin_shift, bool problem_major,
-              BinPlan* plan, std::string* err) {
+// packed longest first into cooperative rounds of at most long_capacity blocks (single-block
+// segments beyond the last full wave of the ordinary launch fill free slots of the last round).
+int plan_bins(const std::vector<SegSource>& src, int long_capacity, int single_capacity, int bin_shift,
+              bool problem_major, BinPlan* plan, std::string* err) {
     struct LongSeg { int32_t q, prob; int64_t len; };
     const size_t ns = src.size();
     std::vector<std::vector<std::vector<int32_t>>> groups(kNumVariants, std::vector<std::vector<int32_t>>(ns));
@@ -297,36 +299,58 @@ int plan_bins(const std::vector<SegSource>& src, int long_capacity, int bin_shif
 
     std::stable_sort(longs.begin(), longs.end(), [](const LongSeg& a, const LongSeg& b) { return a.len > b.len; });
     std::vector<LongWork> lw;
-    {
-        std::vector<LongSeg> single;
-        for (const LongSeg& l : longs)
-            if (l.len <= kLongCapacity) single.push_back(l);
-        if (problem_major)
-            std::stable_sort(single.begin(), single.end(), [](const LongSeg& a, const LongSeg& b) { return a.prob < b.prob; });
-        for (const LongSeg& l : single) lw.push_back(LongWork{l.q, 0, 1, 0, l.prob, 0});
-    }
-    plan->single_blocks = (int)lw.size();
+    std::vector<LongSeg> single;
+    for (const LongSeg& l : longs)
+        if (l.len <= kLongCapacity) single.push_back(l);
+    if (problem_major)
+        std::stable_sort(single.begin(), single.end(), [](const LongSeg& a, const LongSeg& b) { return a.prob < b.prob; });
     // cooperative rounds: B = ceil(L / kCoopCapacity) blocks per segment, at most the
     // device's co-resident capacity per round
-    BinPlan::Round cur{(int)lw.size(), 0, 0, 0};
+    auto blocks_of = [](const LongSeg& l) {
+        return l.len <= kLongCapacity ? 1 : (int)((l.len + kCoopCapacity - 1) / kCoopCapacity);
+    };
+    std::vector<std::vector<LongSeg>> rsegs;
+    std::vector<int> rblocks;
     for (const LongSeg& l : longs) {
         if (l.len <= kLongCapacity) continue;
-        const int B = (int)((l.len + kCoopCapacity - 1) / kCoopCapacity);
+        const int B = blocks_of(l);
         if (B > long_capacity) {
             *err = "a segment of " + std::to_string(l.len) + " nonzeros needs " + std::to_string(B) +
                    " co-resident blocks; this device holds " + std::to_string(long_capacity);
             return NMFKL_E_UNSUPPORTED;
         }
-        if (cur.nblocks + B > long_capacity) {
-            plan->rounds.push_back(cur);
-            cur = BinPlan::Round{(int)lw.size(), 0, 0, 0};
+        if (rblocks.empty() || rblocks.back() + B > long_capacity) {
+            rsegs.emplace_back();
+            rblocks.push_back(0);
         }
-        for (int p = 0; p < B; ++p) lw.push_back(LongWork{l.q, p, B, cur.ngroups, l.prob, 0});
-        cur.nblocks += B;
-        cur.ngroups += 1;
-        cur.pmax = std::max(cur.pmax, B);
+        rsegs.back().push_back(l);
+        rblocks.back() += B;
     }
-    if (cur.nblocks > 0) plan->rounds.push_back(cur);
+    // single-block segments that would start a last, partial wave of the single-block launch
+    // run in free slots of the last cooperative round instead (as B = 1)
+    if (single_capacity > 0 && (int)single.size() > single_capacity && !rsegs.empty()) {
+        const int over = (int)single.size() % single_capacity;
+        if (over > 0 && over <= long_capacity - rblocks.back()) {
+            for (int k = 0; k < over; ++k) {
+                rsegs.back().push_back(single.back());
+                single.pop_back();
+                rblocks.back() += 1;
+            }
+        }
+    }
+    for (const LongSeg& l : single) lw.push_back(LongWork{l.q, 0, 1, 0, l.prob, 0});
+    plan->single_blocks = (int)lw.size();
+    for (const auto& segs_of_round : rsegs) {
+        BinPlan::Round cur{(int)lw.size(), 0, 0, 0};
+        for (const LongSeg& l : segs_of_round) {
+            const int B = blocks_of(l);
+            for (int p = 0; p < B; ++p) lw.push_back(LongWork{l.q, p, B, cur.ngroups, l.prob, 0});
+            cur.nblocks += B;
+            cur.ngroups += 1;
+            cur.pmax = std::max(cur.pmax, B);
+        }
+        plan->rounds.push_back(cur);
+    }
     for (const auto& r : plan->rounds) {
         plan->max_groups = std::max(plan->max_groups, r.ngroups);
         plan->max_pmax = std::max(plan->max_pmax, r.pmax);
@@ -734,6 +758,7 @@ int create_ooc(const nmfkl_problem& pr, const nmfkl_params& prm, void* hip_strea
     int ncu = 0;
     OOC_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
     h->long_capacity = long_kernel_blocks_per_cu() * ncu;
+    h->single_capacity = long_single_blocks_per_cu() * ncu;
     if (h->long_capacity <= 0) {
         fail(h, NMFKL_E_DEVICE, "occupancy query of the long-segment kernel failed");
         return bail(NMFKL_E_DEVICE);
@@ -749,7 +774,7 @@ int create_ooc(const nmfkl_problem& pr, const nmfkl_params& prm, void* hip_strea
         for (auto& c : h->chunks[half]) {
             std::vector<int64_t> local(lptr.begin() + c.lptr, lptr.begin() + c.lptr + (c.seg1 - c.seg0) + 1);
             std::string why_plan;
-            const int rc = plan_bins({SegSource{&local, pr.r, 0}}, h->long_capacity, prm.bin_shift, false, &c.plan,
+            const int rc = plan_bins({SegSource{&local, pr.r, 0}}, h->long_capacity, h->single_capacity, prm.bin_shift, false, &c.plan,
                                      &why_plan);
             if (rc) {
                 fail(h, rc, why_plan);
@@ -910,6 +935,7 @@ int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_str
         int ncu = 0;
         CREATE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
         h->long_capacity = long_kernel_blocks_per_cu() * ncu;
+        h->single_capacity = long_single_blocks_per_cu() * ncu;
         if (h->long_capacity <= 0) {
             fail(h, NMFKL_E_DEVICE, "occupancy query of the long-segment kernel failed");
             return bail(NMFKL_E_DEVICE);
@@ -919,10 +945,10 @@ int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_str
         CREATE_HIP(hipMemcpy(h->hptr_csc.data(), pr.csc_ptr, h->hptr_csc.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
         CREATE_HIP(hipMemcpy(h->hptr_csr.data(), pr.csr_ptr, h->hptr_csr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
         std::string why_plan;
-        int rc = plan_bins({SegSource{&h->hptr_csc, pr.r, 0}}, h->long_capacity, prm.bin_shift, false, &h->binF,
+        int rc = plan_bins({SegSource{&h->hptr_csc, pr.r, 0}}, h->long_capacity, h->single_capacity, prm.bin_shift, false, &h->binF,
                            &why_plan);
         if (!rc)
-            rc = plan_bins({SegSource{&h->hptr_csr, pr.r, 0}}, h->long_capacity, prm.bin_shift, false, &h->binW,
+            rc = plan_bins({SegSource{&h->hptr_csr, pr.r, 0}}, h->long_capacity, h->single_capacity, prm.bin_shift, false, &h->binW,
                            &why_plan);
         if (rc) {
             fail(h, rc, why_plan);
@@ -1107,6 +1133,7 @@ struct nmfkl_batch {
     unsigned* dev_err = nullptr;
     int64_t* t_dev = nullptr;
     int long_capacity = 0;
+    int single_capacity = 0;
     int graph_coop = -1;
     std::vector<std::pair<int, hipGraphExec_t>> graphs;
     std::string err;
@@ -1160,8 +1187,8 @@ int batch_plan(nmfkl_batch* b) {
     }
     std::string why;
     const bool pm = (b->prm.tuning & 2) != 0;
-    int rc = plan_bins(srcF, b->long_capacity, b->prm.bin_shift, pm, &b->plan[0], &why);
-    if (!rc) rc = plan_bins(srcW, b->long_capacity, b->prm.bin_shift, pm, &b->plan[1], &why);
+    int rc = plan_bins(srcF, b->long_capacity, b->single_capacity, b->prm.bin_shift, pm, &b->plan[0], &why);
+    if (!rc) rc = plan_bins(srcW, b->long_capacity, b->single_capacity, b->prm.bin_shift, pm, &b->plan[1], &why);
     if (rc) return bfail(b, rc, why);
     const int groups = std::max(std::max(b->plan[0].max_groups, b->plan[1].max_groups), 1);
     const int pmax = std::max(std::max(b->plan[0].max_pmax, b->plan[1].max_pmax), 1);
@@ -1264,6 +1291,7 @@ int nmfkl_batch_create(int32_t nprob, const nmfkl_problem* probs, const nmfkl_pa
         b->hs.push_back(h);
     }
     b->long_capacity = b->hs[0]->long_capacity;
+    b->single_capacity = b->hs[0]->single_capacity;
     std::vector<SweepArgs> args(2 * (size_t)nprob);
     std::vector<PermJob> jobs(2 * (size_t)nprob);
     for (int half = 0; half < 2; ++half) {

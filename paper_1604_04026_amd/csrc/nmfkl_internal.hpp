@@ -201,6 +201,8 @@ hipError_t launch_sweep_long(const SweepArgs* tab, const LongWork* work, int nbl
                              int ngroups, unsigned* err, int pmax, bool cooperative, hipStream_t stream);
 // Co-resident blocks of the cooperative long-segment kernel per compute unit (0 on failure).
 int long_kernel_blocks_per_cu();
+// ... and of the single-block long-segment kernel (0 on failure).
+int long_single_blocks_per_cu();
 hipError_t launch_model_objective(const int64_t* csc_ptr, const int32_t* csc_idx,
                                   const float* csc_val, int m, const float* W, const float* F, int r,
                                   double* Mcsc, double* partials, int nblocks, hipStream_t stream);

@@ -944,6 +944,14 @@ hipError_t launch_sweep_long(const SweepArgs* tab, const LongWork* work, int nbl
                                       dim3(kLongThreads), args, 0, stream);
 }
 
+int long_single_blocks_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_sweep_long<false, kLongE>),
+                                                     kLongThreads, 0) != hipSuccess)
+        return 0;
+    return nb;
+}
+
 int long_kernel_blocks_per_cu() {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_sweep_long<true, kCoopE>),
