@@ -23,11 +23,11 @@ struct BinPlan {
     int32_t* segs = nullptr;    // device
     int nblocks = 0;
     // long segments: those fitting one block in an ordinary launch (single_blocks entries at
-    // the start of long_work), the others in cooperative launches ("rounds"), each within
-    // the co-residency capacity
-    LongWork* long_work = nullptr;  // device: single-block entries, then all rounds
+    // the start of long_work), the others in one cooperative queue launch of at most the
+    // co-residency capacity (the one entry of `rounds`, empty when there is none)
+    LongWork* long_work = nullptr;  // device: single-block entries, then the queue's parts
     int single_blocks = 0;
-    struct Round { int first, nblocks, ngroups, pmax; };
+    struct Round { int first, nblocks, ngroups, pmax, grid; };  // nblocks: parts; grid: blocks
     std::vector<Round> rounds;
     int max_groups = 0, max_pmax = 0;
     // algorithmic (gather-model) bytes and updates of the fused and of the long launches
@@ -223,9 +223,9 @@ void free_plan(BinPlan* p) {
 // blocks start early); inside a variant each problem's segments are sorted longest first and
 // cut into blocks of kFusedThreads / G segments of that problem, and the blocks of all
 // problems are ordered by their first segment, longest first.  Longer segments: B =
-// ceil(L / kLongCapacity) blocks each; those with B = 1 in one ordinary launch, the others
-// packed longest first into cooperative rounds of at most long_capacity blocks (single-block
-// segments beyond the last full wave of the ordinary launch fill free slots of the last round).
+// ceil(L / kLongCapacity) blocks each; those with B = 1 in one ordinary launch, the others in
+// one cooperative launch that works through them as a queue, largest first (single-block
+// segments beyond the last full wave of the ordinary launch join the end of the queue).
 int plan_bins(const std::vector<SegSource>& src, int long_capacity, int single_capacity, int bin_shift,
               bool problem_major, BinPlan* plan, std::string* err) {
     struct LongSeg { int32_t q, prob; int64_t len; };
@@ -299,56 +299,45 @@ int plan_bins(const std::vector<SegSource>& src, int long_capacity, int single_c
 
     std::stable_sort(longs.begin(), longs.end(), [](const LongSeg& a, const LongSeg& b) { return a.len > b.len; });
     std::vector<LongWork> lw;
-    std::vector<LongSeg> single;
-    for (const LongSeg& l : longs)
-        if (l.len <= kLongCapacity) single.push_back(l);
-    if (problem_major)
-        std::stable_sort(single.begin(), single.end(), [](const LongSeg& a, const LongSeg& b) { return a.prob < b.prob; });
-    // cooperative rounds: B = ceil(L / kCoopCapacity) blocks per segment, at most the
-    // device's co-resident capacity per round
-    auto blocks_of = [](const LongSeg& l) {
-        return l.len <= kLongCapacity ? 1 : (int)((l.len + kCoopCapacity - 1) / kCoopCapacity);
-    };
-    std::vector<std::vector<LongSeg>> rsegs;
-    std::vector<int> rblocks;
+    // Segments of at most kLongCapacity nonzeros run one block each in an ordinary launch;
+    // longer ones go to the cooperative queue (k_sweep_long_queue), largest B = ceil(L /
+    // kCoopCapacity) first.
+    auto blocks_of = [](const LongSeg& l) { return (int)((l.len + kCoopCapacity - 1) / kCoopCapacity); };
+    std::vector<LongSeg> single, queued;
     for (const LongSeg& l : longs) {
-        if (l.len <= kLongCapacity) continue;
-        const int B = blocks_of(l);
-        if (B > long_capacity) {
-            *err = "a segment of " + std::to_string(l.len) + " nonzeros needs " + std::to_string(B) +
-                   " co-resident blocks; this device holds " + std::to_string(long_capacity);
-            return NMFKL_E_UNSUPPORTED;
-        }
-        if (rblocks.empty() || rblocks.back() + B > long_capacity) {
-            rsegs.emplace_back();
-            rblocks.push_back(0);
-        }
-        rsegs.back().push_back(l);
-        rblocks.back() += B;
+        if (l.len <= kLongCapacity) single.push_back(l);
+        else queued.push_back(l);
     }
     // single-block segments that would start a last, partial wave of the single-block launch
-    // run in free slots of the last cooperative round instead (as B = 1)
-    if (single_capacity > 0 && (int)single.size() > single_capacity && !rsegs.empty()) {
+    // join the end of the queue instead (as B = 1)
+    if (!queued.empty() && single_capacity > 0 && (int)single.size() > single_capacity) {
         const int over = (int)single.size() % single_capacity;
-        if (over > 0 && over <= long_capacity - rblocks.back()) {
-            for (int k = 0; k < over; ++k) {
-                rsegs.back().push_back(single.back());
-                single.pop_back();
-                rblocks.back() += 1;
-            }
+        for (int k = 0; k < over; ++k) {
+            queued.push_back(single.back());
+            single.pop_back();
         }
     }
+    if (problem_major)
+        std::stable_sort(single.begin(), single.end(), [](const LongSeg& a, const LongSeg& b) { return a.prob < b.prob; });
     for (const LongSeg& l : single) lw.push_back(LongWork{l.q, 0, 1, 0, l.prob, 0});
     plan->single_blocks = (int)lw.size();
-    for (const auto& segs_of_round : rsegs) {
-        BinPlan::Round cur{(int)lw.size(), 0, 0, 0};
-        for (const LongSeg& l : segs_of_round) {
+    if (!queued.empty()) {
+        BinPlan::Round cur{(int)lw.size(), 0, 0, 0, 0};
+        for (const LongSeg& l : queued) {
             const int B = blocks_of(l);
-            for (int p = 0; p < B; ++p) lw.push_back(LongWork{l.q, p, B, cur.ngroups, l.prob, 0});
+            if (B > long_capacity) {
+                *err = "a segment of " + std::to_string(l.len) + " nonzeros needs " + std::to_string(B) +
+                       " co-resident blocks; this device holds " + std::to_string(long_capacity);
+                return NMFKL_E_UNSUPPORTED;
+            }
+            // B = 1 parts exchange nothing: they share group 0
+            const int group = B > 1 ? cur.ngroups++ : 0;
+            for (int p = 0; p < B; ++p) lw.push_back(LongWork{l.q, p, B, group, l.prob, 0});
             cur.nblocks += B;
-            cur.ngroups += 1;
             cur.pmax = std::max(cur.pmax, B);
         }
+        cur.ngroups = std::max(cur.ngroups, 1);
+        cur.grid = std::min(cur.nblocks, long_capacity);
         plan->rounds.push_back(cur);
     }
     for (const auto& r : plan->rounds) {
@@ -482,8 +471,8 @@ hipError_t enqueue_plan(const BinPlan& plan, const SweepArgs* tab, unsigned long
     const int tl = (timed && any_long) ? timer_begin(timed, long_kind) : -1;
     if ((e = launch_sweep_long_single(tab, plan.long_work, plan.single_blocks, s)) != hipSuccess) return e;
     for (const auto& rd : plan.rounds)
-        if ((e = launch_sweep_long(tab, plan.long_work + rd.first, rd.nblocks, coop_words, rd.ngroups, dev_err,
-                                   rd.pmax, cooperative, s)) != hipSuccess)
+        if ((e = launch_sweep_long(tab, plan.long_work + rd.first, rd.nblocks, rd.grid, coop_words, rd.ngroups,
+                                   dev_err, rd.pmax, cooperative, s)) != hipSuccess)
             return e;
     if (timed) timer_end(timed, tl);
     const int tf = (timed && plan.nblocks) ? timer_begin(timed, fused_kind) : -1;
@@ -785,7 +774,7 @@ int create_ooc(const nmfkl_problem& pr, const nmfkl_params& prm, void* hip_strea
             if (c.plan.single_blocks > 0 || !c.plan.rounds.empty()) h->long_half[half] = true;
         }
     if (h->long_half[0] || h->long_half[1]) OOC_HIP(dalloc(&h->Apc, (size_t)Pmax * ((pr.r + 3) & ~3)));
-    OOC_HIP(dalloc(&h->coop_words, (size_t)groups * 2 * pmax * kCoopValues));
+    OOC_HIP(dalloc(&h->coop_words, (size_t)groups * 2 * pmax * kCoopValues + 1));
     OOC_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->h_lptr), lptr.size() * sizeof(int64_t), hipHostMallocDefault));
     std::memcpy(h->h_lptr, lptr.data(), lptr.size() * sizeof(int64_t));
     for (int b = 0; b < 2; ++b) {
@@ -960,8 +949,9 @@ int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_str
             CREATE_HIP(dalloc(&h->Apc, (size_t)Pmax * ((pr.r + 3) & ~3)));
         const int groups = std::max(h->binF.max_groups, h->binW.max_groups);
         const int pmax = std::max(h->binF.max_pmax, h->binW.max_pmax);
-        // k_sweep_long<true> addresses words + group * (2 * pmax * kCoopValues) + ...
-        CREATE_HIP(dalloc(&h->coop_words, (size_t)std::max(groups, 1) * 2 * std::max(pmax, 1) * kCoopValues));
+        // the queue kernel addresses words + group * (2 * pmax * kCoopValues) + ..., then the
+        // ticket counter after the last group
+        CREATE_HIP(dalloc(&h->coop_words, (size_t)std::max(groups, 1) * 2 * std::max(pmax, 1) * kCoopValues + 1));
         CREATE_HIP(dalloc(&h->dev_err, 1));
         CREATE_HIP(hipMemsetAsync(h->dev_err, 0, sizeof(unsigned), h->stream));
     }
@@ -1192,7 +1182,7 @@ int batch_plan(nmfkl_batch* b) {
     if (rc) return bfail(b, rc, why);
     const int groups = std::max(std::max(b->plan[0].max_groups, b->plan[1].max_groups), 1);
     const int pmax = std::max(std::max(b->plan[0].max_pmax, b->plan[1].max_pmax), 1);
-    const size_t nw = (size_t)groups * 2 * pmax * kCoopValues;
+    const size_t nw = (size_t)groups * 2 * pmax * kCoopValues + 1;
     if (nw > b->coop_words_n) {
         if (b->coop_words) (void)hipFree(b->coop_words);
         b->coop_words = nullptr;

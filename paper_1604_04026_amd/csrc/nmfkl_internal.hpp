@@ -193,12 +193,15 @@ hipError_t launch_sweep_long_single(const SweepArgs* tab, const LongWork* work, 
 // Partial sums a cooperating block publishes per reduction (at most S1 and S2 of every
 // coordinate of an 8-wide chunk), one tagged 64-bit word each.
 constexpr int kCoopValues = 2 * kChunk;
-// Cooperative launch over long segments; zeroes the group's tagged partial words first
-// (2 * pmax * kCoopValues words per group, pmax = largest B in the launch).
-// cooperative = false: ordinary launch of the same grid (inside a captured graph), which
-// relies on the grid fitting the device's co-resident capacity; the waits stay bounded.
-hipError_t launch_sweep_long(const SweepArgs* tab, const LongWork* work, int nblocks, unsigned long long* words,
-                             int ngroups, unsigned* err, int pmax, bool cooperative, hipStream_t stream);
+// Long segments over several co-resident blocks: one cooperative launch of `grid` blocks
+// that take the nparts parts of the work list through a ticket counter.  Zeroes the groups'
+// tagged partial words and the counter first (2 * pmax * kCoopValues words per group, pmax =
+// largest B in the list, then one counter word).  cooperative = false: ordinary launch of
+// the same grid (inside a captured graph), which relies on the grid fitting the device's
+// co-resident capacity; the waits stay bounded.
+hipError_t launch_sweep_long(const SweepArgs* tab, const LongWork* work, int nparts, int grid,
+                             unsigned long long* words, int ngroups, unsigned* err, int pmax, bool cooperative,
+                             hipStream_t stream);
 // Co-resident blocks of the cooperative long-segment kernel per compute unit (0 on failure).
 int long_kernel_blocks_per_cu();
 // ... and of the single-block long-segment kernel (0 on failure).

@@ -868,19 +868,14 @@ hipError_t launch_sweep_fused(const SweepArgs* tab, const BlockWork* work, const
 constexpr int kLongCW = 4;
 constexpr int kCoopCW = 4;
 
+// One block's part of a long segment: the segment's x and column sums into LDS, the sweep,
+// and x back (part 0).  COOP: the blocks of the segment exchange through CoopReducer.
 template <bool COOP, int E>
-__global__ void __launch_bounds__(kLongThreads, E <= kLongE ? 3 : 2)
-k_sweep_long(const SweepArgs* __restrict__ tab, const LongWork* __restrict__ work,
-             unsigned long long* __restrict__ words, unsigned* __restrict__ err, int pmax) {
+__device__ __forceinline__ void long_part(const SweepArgs* __restrict__ tab, const LongWork& wk,
+                                          unsigned long long* words, unsigned* err, int pmax, float* xs,
+                                          float* red_lds, double* tmp, double* bcast, int32_t* s_id, float* s_v,
+                                          double* sA_lds) {
     constexpr int CAP = kLongThreads * E;
-    __shared__ float xs[NMFKL_R_MAX];
-    __shared__ float red_lds[2 * (kLongThreads / 64) * kMaxRed];
-    __shared__ double tmp[CoopReducer<kLongThreads>::J * kMaxRed];
-    __shared__ double bcast[kMaxRed];
-    __shared__ int32_t s_id[CAP];
-    __shared__ float s_v[CAP];
-    __shared__ double sA_lds[NMFKL_R_MAX];
-    const LongWork wk = work[blockIdx.x];
     SweepArgs a = tab[wk.prob];
     const int lane = threadIdx.x;
     LdsElemsNoWU<E, kLongThreads> st;
@@ -914,6 +909,48 @@ k_sweep_long(const SweepArgs* __restrict__ tab, const LongWork* __restrict__ wor
         for (int s = lane; s < a.r; s += kLongThreads) a.X[(int64_t)wk.seg * a.r + a.ids[s]] = xs[s];
 }
 
+template <int E>
+__global__ void __launch_bounds__(kLongThreads, 3)
+k_sweep_long_single(const SweepArgs* __restrict__ tab, const LongWork* __restrict__ work) {
+    __shared__ float xs[NMFKL_R_MAX];
+    __shared__ float red_lds[2 * (kLongThreads / 64) * kMaxRed];
+    __shared__ int32_t s_id[kLongThreads * E];
+    __shared__ float s_v[kLongThreads * E];
+    __shared__ double sA_lds[NMFKL_R_MAX];
+    long_part<false, E>(tab, work[blockIdx.x], nullptr, nullptr, 0, xs, red_lds, nullptr, nullptr, s_id, s_v,
+                        sA_lds);
+}
+
+// Every long segment of a launch in one cooperative launch of at most the co-resident
+// capacity: the blocks take parts from the work list in order through a ticket counter.  The
+// parts of a segment are consecutive, so the blocks that take them work on it together.  A
+// block waits for its partners only once every earlier part has been taken by a running
+// block; the blocks holding parts of earlier segments finish without waiting on later
+// parts, and each block takes a new ticket as soon as it is free, so every wait ends (given
+// B <= the grid, which the planner checks).  The list holds the largest B first.
+template <int E>
+__global__ void __launch_bounds__(kLongThreads, 2)
+k_sweep_long_queue(const SweepArgs* __restrict__ tab, const LongWork* __restrict__ work, int nparts,
+                   unsigned long long* __restrict__ words, unsigned long long* __restrict__ ticket,
+                   unsigned* __restrict__ err, int pmax) {
+    __shared__ float xs[NMFKL_R_MAX];
+    __shared__ float red_lds[2 * (kLongThreads / 64) * kMaxRed];
+    __shared__ double tmp[CoopReducer<kLongThreads>::J * kMaxRed];
+    __shared__ double bcast[kMaxRed];
+    __shared__ int32_t s_id[kLongThreads * E];
+    __shared__ float s_v[kLongThreads * E];
+    __shared__ double sA_lds[NMFKL_R_MAX];
+    __shared__ int s_ticket;
+    for (;;) {
+        if (threadIdx.x == 0) s_ticket = (int)atomicAdd(ticket, 1ull);
+        __syncthreads();
+        const int t = s_ticket;
+        __syncthreads();
+        if (t >= nparts) break;
+        long_part<true, E>(tab, work[t], words, err, pmax, xs, red_lds, tmp, bcast, s_id, s_v, sA_lds);
+    }
+}
+
 __global__ void k_zero_u64(unsigned long long* p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0ull;
@@ -922,31 +959,34 @@ __global__ void k_zero_u64(unsigned long long* p, int64_t n) {
 hipError_t launch_sweep_long_single(const SweepArgs* tab, const LongWork* work, int nblocks,
                                     hipStream_t stream) {
     if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_sweep_long<false, kLongE>), dim3(nblocks), dim3(kLongThreads), 0, stream, tab, work,
-                       (unsigned long long*)nullptr, (unsigned*)nullptr, 0);
+    hipLaunchKernelGGL((k_sweep_long_single<kLongE>), dim3(nblocks), dim3(kLongThreads), 0, stream, tab, work);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_long(const SweepArgs* tab, const LongWork* work, int nblocks, unsigned long long* words,
-                             int ngroups, unsigned* err, int pmax, bool cooperative, hipStream_t stream) {
-    if (nblocks <= 0) return hipSuccess;
+hipError_t launch_sweep_long(const SweepArgs* tab, const LongWork* work, int nparts, int grid,
+                             unsigned long long* words, int ngroups, unsigned* err, int pmax, bool cooperative,
+                             hipStream_t stream) {
+    if (nparts <= 0 || grid <= 0) return hipSuccess;
+    // the groups' words, then the ticket counter
     const int64_t nwords = (int64_t)ngroups * 2 * pmax * kCoopValues;
-    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((nwords + 255) / 256)), dim3(256), 0, stream, words, nwords);
+    unsigned long long* ticket = words + nwords;
+    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((nwords + 1 + 255) / 256)), dim3(256), 0, stream, words,
+                       nwords + 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (!cooperative) {
-        hipLaunchKernelGGL((k_sweep_long<true, kCoopE>), dim3(nblocks), dim3(kLongThreads), 0, stream, tab, work,
-                           words, err, pmax);
+        hipLaunchKernelGGL((k_sweep_long_queue<kCoopE>), dim3(grid), dim3(kLongThreads), 0, stream, tab, work,
+                           nparts, words, ticket, err, pmax);
         return hipGetLastError();
     }
-    void* args[] = {&tab, &work, &words, &err, &pmax};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_sweep_long<true, kCoopE>), dim3(nblocks),
+    void* args[] = {&tab, &work, &nparts, &words, &ticket, &err, &pmax};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_sweep_long_queue<kCoopE>), dim3(grid),
                                       dim3(kLongThreads), args, 0, stream);
 }
 
 int long_single_blocks_per_cu() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_sweep_long<false, kLongE>),
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_sweep_long_single<kLongE>),
                                                      kLongThreads, 0) != hipSuccess)
         return 0;
     return nb;
@@ -954,7 +994,7 @@ int long_single_blocks_per_cu() {
 
 int long_kernel_blocks_per_cu() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_sweep_long<true, kCoopE>),
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_sweep_long_queue<kCoopE>),
                                                      kLongThreads, 0) != hipSuccess)
         return 0;
     return nb;
