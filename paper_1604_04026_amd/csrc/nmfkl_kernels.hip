@@ -921,6 +921,21 @@ k_sweep_long_single(const SweepArgs* __restrict__ tab, const LongWork* __restric
                         sA_lds);
 }
 
+// Long segments whose parts all fit the co-resident capacity: one part per block.
+template <int E>
+__global__ void __launch_bounds__(kLongThreads, 2)
+k_sweep_long_flat(const SweepArgs* __restrict__ tab, const LongWork* __restrict__ work,
+                  unsigned long long* __restrict__ words, unsigned* __restrict__ err, int pmax) {
+    __shared__ float xs[NMFKL_R_MAX];
+    __shared__ float red_lds[2 * (kLongThreads / 64) * kMaxRed];
+    __shared__ double tmp[CoopReducer<kLongThreads>::J * kMaxRed];
+    __shared__ double bcast[kMaxRed];
+    __shared__ int32_t s_id[kLongThreads * E];
+    __shared__ float s_v[kLongThreads * E];
+    __shared__ double sA_lds[NMFKL_R_MAX];
+    long_part<true, E>(tab, work[blockIdx.x], words, err, pmax, xs, red_lds, tmp, bcast, s_id, s_v, sA_lds);
+}
+
 // Every long segment of a launch in one cooperative launch of at most the co-resident
 // capacity: the blocks take parts from the work list in order through a ticket counter.  The
 // parts of a segment are consecutive, so the blocks that take them work on it together.  A
@@ -944,7 +959,8 @@ k_sweep_long_queue(const SweepArgs* __restrict__ tab, const LongWork* __restrict
     for (;;) {
         if (threadIdx.x == 0) s_ticket = (int)atomicAdd(ticket, 1ull);
         __syncthreads();
-        const int t = s_ticket;
+        // uniform: keeps the work entry and everything derived from it in scalar registers
+        const int t = __builtin_amdgcn_readfirstlane(s_ticket);
         __syncthreads();
         if (t >= nparts) break;
         long_part<true, E>(tab, work[t], words, err, pmax, xs, red_lds, tmp, bcast, s_id, s_v, sA_lds);
@@ -974,6 +990,17 @@ hipError_t launch_sweep_long(const SweepArgs* tab, const LongWork* work, int npa
                        nwords + 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (grid == nparts) {
+        // every part has a block of its own
+        if (!cooperative) {
+            hipLaunchKernelGGL((k_sweep_long_flat<kCoopE>), dim3(grid), dim3(kLongThreads), 0, stream, tab, work,
+                               words, err, pmax);
+            return hipGetLastError();
+        }
+        void* fargs[] = {&tab, &work, &words, &err, &pmax};
+        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_sweep_long_flat<kCoopE>), dim3(grid),
+                                          dim3(kLongThreads), fargs, 0, stream);
+    }
     if (!cooperative) {
         hipLaunchKernelGGL((k_sweep_long_queue<kCoopE>), dim3(grid), dim3(kLongThreads), 0, stream, tab, work,
                            nparts, words, ticket, err, pmax);
