@@ -69,12 +69,15 @@ struct nmfkl_handle {
     int32_t* csr2csc = nullptr;
     double* obj_partials = nullptr;
     int obj_blocks = 0;
-    double* sums2 = nullptr;      // 2 x r natural-order sums (objective)
-    double* dscal = nullptr;      // device scalar (objective total)
-    double* host_scal = nullptr;  // pinned host scalar
+    // device results read back together by the objective: [total, 2 x r natural-order sums,
+    // error flags], with a pinned host mirror of the same layout
+    double* dres = nullptr;
+    double* host_res = nullptr;
+    double* sums2 = nullptr;      // dres + 1
+    double* dscal = nullptr;      // dres
     unsigned long long* stats = nullptr;
     unsigned long long* coop_words = nullptr;  // tagged cross-block partial sums of long segments
-    unsigned* dev_err = nullptr;       // device-side error flags (bounded waits)
+    unsigned* dev_err = nullptr;       // device-side error flags (bounded waits), in dres's last word
     int long_capacity = 0;             // co-resident blocks of the cooperative long-segment kernel
     int single_capacity = 0;           // co-resident blocks of the single-block long-segment kernel
     BinPlan binF, binW;
@@ -120,6 +123,21 @@ int fail(nmfkl_handle* h, int code, const std::string& msg) {
 
 int hip_fail(nmfkl_handle* h, hipError_t e, const char* what) {
     return fail(h, NMFKL_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t results_words(int r) { return 2 + 2 * (size_t)r; }
+
+// The results block [total, 2 x r sums, error flags] on the device and its pinned mirror.
+hipError_t alloc_results(nmfkl_handle* h) {
+    const size_t n = results_words(h->prob.r);
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&h->dres), n * sizeof(double));
+    if (e != hipSuccess) return e;
+    e = hipHostMalloc(reinterpret_cast<void**>(&h->host_res), n * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    h->dscal = h->dres;
+    h->sums2 = h->dres + 1;
+    h->dev_err = reinterpret_cast<unsigned*>(h->dres + 1 + 2 * (size_t)h->prob.r);
+    return hipSuccess;
 }
 
 #define HIP_TRY(h, expr)                                   \
@@ -184,11 +202,11 @@ void release(nmfkl_handle* h) {
     h->event_pool.clear();
     auto f = [](void* p) { if (p) (void)hipFree(p); };
     f(h->Ap); f(h->Apc); f(h->sumA); f(h->partials); f(h->ids); f(h->Mcsc); f(h->Mcsr);
-    f(h->csc2csr); f(h->csr2csc); f(h->obj_partials); f(h->sums2); f(h->dscal); f(h->stats);
+    f(h->csc2csr); f(h->csr2csc); f(h->obj_partials); f(h->dres); f(h->stats);
     f(h->binF.work); f(h->binF.segs); f(h->binW.work); f(h->binW.segs);
     f(h->binF.long_work); f(h->binW.long_work);
-    f(h->coop_words); f(h->dev_err); f(h->argtab); f(h->jobtab);
-    if (h->host_scal) (void)hipHostFree(h->host_scal);
+    f(h->coop_words); f(h->argtab); f(h->jobtab);
+    if (h->host_res) (void)hipHostFree(h->host_res);
     for (int k = 0; k < 2; ++k) {
         for (auto& c : h->chunks[k]) {
             auto g = [](void* q) { if (q) (void)hipFree(q); };
@@ -769,12 +787,9 @@ int create_ooc(const nmfkl_problem& pr, const nmfkl_params& prm, void* hip_strea
     OOC_HIP(dalloc(&h->ids, NMFKL_R_MAX));
     h->obj_blocks = 4096;
     OOC_HIP(dalloc(&h->obj_partials, h->obj_blocks));
-    OOC_HIP(dalloc(&h->sums2, 2 * (size_t)pr.r));
-    OOC_HIP(dalloc(&h->dscal, 1));
+    OOC_HIP(alloc_results(h));
     OOC_HIP(dalloc(&h->stats, 6));
     OOC_HIP(hipMemsetAsync(h->stats, 0, 6 * sizeof(unsigned long long), h->stream));
-    OOC_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->host_scal), sizeof(double), hipHostMallocDefault));
-    OOC_HIP(dalloc(&h->dev_err, 1));
     OOC_HIP(hipMemsetAsync(h->dev_err, 0, sizeof(unsigned), h->stream));
     int ncu = 0;
     OOC_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
@@ -947,11 +962,9 @@ int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_str
     CREATE_HIP(dalloc(&h->Mcsr, nnz));
     h->obj_blocks = (int)std::min<int64_t>(4096, std::max<int64_t>(1, pr.m / 8));
     CREATE_HIP(dalloc(&h->obj_partials, h->obj_blocks));
-    CREATE_HIP(dalloc(&h->sums2, 2 * (size_t)pr.r));
-    CREATE_HIP(dalloc(&h->dscal, 1));
+    CREATE_HIP(alloc_results(h));
     CREATE_HIP(dalloc(&h->stats, 6));
     CREATE_HIP(hipMemsetAsync(h->stats, 0, 6 * sizeof(unsigned long long), h->stream));
-    CREATE_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->host_scal), sizeof(double), hipHostMallocDefault));
     {
         int ncu = 0;
         CREATE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
@@ -984,7 +997,6 @@ int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_str
         // the queue kernel addresses words + group * (2 * pmax * kCoopValues) + ..., then the
         // ticket counter after the last group
         CREATE_HIP(dalloc(&h->coop_words, (size_t)std::max(groups, 1) * 2 * std::max(pmax, 1) * kCoopValues + 1));
-        CREATE_HIP(dalloc(&h->dev_err, 1));
         CREATE_HIP(hipMemsetAsync(h->dev_err, 0, sizeof(unsigned), h->stream));
     }
     {
@@ -1075,15 +1087,15 @@ int objective_impl(nmfkl_handle* h, double* D_out, bool carried) {
         if (rc) return rc;
     }
     if (!h->ooc) HIP_TRY(h, launch_sum_f64(h->obj_partials, h->obj_blocks, h->dscal, h->stream));
-    double part = 0.0;
-    std::vector<double> sums(2 * (size_t)pr.r);
-    HIP_TRY(h, hipMemcpyAsync(h->host_scal, h->dscal, sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(h, hipMemcpyAsync(sums.data(), h->sums2, sums.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    unsigned derr = 0;
-    HIP_TRY(h, hipMemcpyAsync(&derr, h->dev_err, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));
+    // one copy of [total, sums, error flags] into pinned memory
+    HIP_TRY(h, hipMemcpyAsync(h->host_res, h->dres, results_words(pr.r) * sizeof(double), hipMemcpyDeviceToHost,
+                              h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
+    unsigned derr = 0;
+    std::memcpy(&derr, h->host_res + 1 + 2 * (size_t)pr.r, sizeof(unsigned));
     if (derr) return fail(h, NMFKL_E_DEVICE, "a cross-block wait of a long segment timed out");
-    part = *h->host_scal;
+    const double part = h->host_res[0];
+    const double* sums = h->host_res + 1;
     double total = 0.0;
     for (int k = 0; k < pr.r; ++k) {
         if (!std::isfinite(sums[k]) || !std::isfinite(sums[pr.r + k]))
