@@ -201,6 +201,15 @@ int nmfkl_objective(nmfkl_handle* h, double* D_out);
  * nmfkl_objective when no model is carried yet. */
 int nmfkl_objective_carried(nmfkl_handle* h, double* D_out);
 
+/* nmfkl_objective_carried in two steps, so that a loop can keep the device busy: enqueue
+ * computes eq. 1 on the handle's stream and copies the result into the handle's pinned
+ * host memory without synchronising; read synchronises the stream and returns the value of
+ * the last enqueue (with the same checks and error codes as nmfkl_objective_carried).  A
+ * later enqueue replaces the pending value.  read without an enqueue since the last read
+ * returns NMFKL_E_INVAL. */
+int nmfkl_objective_enqueue(nmfkl_handle* h);
+int nmfkl_objective_read(nmfkl_handle* h, double* D_out);
+
 /* Tell the handle that the caller changed W or F outside the library: the model values
  * the handle carries between halves are recomputed before the next half-sweep. */
 int nmfkl_invalidate_model(nmfkl_handle* h);

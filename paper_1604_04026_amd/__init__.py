@@ -28,7 +28,8 @@ R_MAX = 128
 
 EXPORTED_SYMBOLS = [
     "nmfkl_params_default", "nmfkl_permutation", "nmfkl_create", "nmfkl_sweep_F", "nmfkl_sweep_W",
-    "nmfkl_objective", "nmfkl_objective_carried", "nmfkl_invalidate_model", "nmfkl_get_stats", "nmfkl_get_timings",
+    "nmfkl_objective", "nmfkl_objective_carried", "nmfkl_objective_enqueue", "nmfkl_objective_read",
+    "nmfkl_invalidate_model", "nmfkl_get_stats", "nmfkl_get_timings",
     "nmfkl_reset_timings", "nmfkl_destroy", "nmfkl_last_error",
     "nmfkl_model_create", "nmfkl_foldin", "nmfkl_model_get_stats", "nmfkl_model_last_error",
     "nmfkl_model_destroy", "nmfkl_server_create", "nmfkl_server_submit", "nmfkl_server_poll",
@@ -137,6 +138,8 @@ def load(path: str | None = None):
     lib.nmfkl_sweep_W.argtypes = [vp, i32]
     lib.nmfkl_objective.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     lib.nmfkl_objective_carried.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    lib.nmfkl_objective_enqueue.argtypes = [vp]
+    lib.nmfkl_objective_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     lib.nmfkl_invalidate_model.argtypes = [vp]
     lib.nmfkl_get_stats.argtypes = [vp, ctypes.POINTER(NmfklStats)]
     lib.nmfkl_get_timings.argtypes = [vp, ctypes.POINTER(NmfklTimings)]
@@ -306,6 +309,16 @@ def nmfkl_objective(h: Handle) -> float:
 def nmfkl_objective_carried(h: Handle) -> float:
     d = ctypes.c_double()
     _check(load().nmfkl_objective_carried(h._ptr, ctypes.byref(d)), h._ptr)
+    return d.value
+
+
+def nmfkl_objective_enqueue(h: Handle):
+    _check(load().nmfkl_objective_enqueue(h._ptr), h._ptr)
+
+
+def nmfkl_objective_read(h: Handle) -> float:
+    d = ctypes.c_double()
+    _check(load().nmfkl_objective_read(h._ptr, ctypes.byref(d)), h._ptr)
     return d.value
 
 

@@ -110,6 +110,7 @@ struct nmfkl_handle {
     std::vector<hipEvent_t> event_pool;
     nmfkl_timings timings{};
     int model = kModelNone;
+    bool objective_pending = false;    // nmfkl_objective_enqueue's value not read yet
     std::string err;
 };
 
@@ -1044,16 +1045,42 @@ int nmfkl_invalidate_model(nmfkl_handle* h) {
 
 namespace {
 int objective_impl(nmfkl_handle* h, double* D_out, bool carried);
+int objective_enqueue(nmfkl_handle* h, bool carried);
+int objective_finish(nmfkl_handle* h, double* D_out);
 }
 
 int nmfkl_objective(nmfkl_handle* h, double* D_out) { return objective_impl(h, D_out, false); }
 
 int nmfkl_objective_carried(nmfkl_handle* h, double* D_out) { return objective_impl(h, D_out, true); }
 
+int nmfkl_objective_enqueue(nmfkl_handle* h) {
+    if (!h) return fail(nullptr, NMFKL_E_INVAL, "null handle");
+    const int rc = objective_enqueue(h, true);
+    if (rc) return rc;
+    h->objective_pending = true;
+    return NMFKL_OK;
+}
+
+int nmfkl_objective_read(nmfkl_handle* h, double* D_out) {
+    if (!h) return fail(nullptr, NMFKL_E_INVAL, "null handle");
+    if (!D_out) return fail(h, NMFKL_E_INVAL, "D_out is null");
+    if (!h->objective_pending) return fail(h, NMFKL_E_INVAL, "no objective enqueued since the last read");
+    h->objective_pending = false;
+    return objective_finish(h, D_out);
+}
+
 namespace {
 int objective_impl(nmfkl_handle* h, double* D_out, bool carried) {
     if (!h) return fail(nullptr, NMFKL_E_INVAL, "null handle");
     if (!D_out) return fail(h, NMFKL_E_INVAL, "D_out is null");
+    const int rc = objective_enqueue(h, carried);
+    if (rc) return rc;
+    h->objective_pending = false;
+    return objective_finish(h, D_out);
+}
+
+// eq. 1's kernels and the copy of the results block into pinned host memory (no wait).
+int objective_enqueue(nmfkl_handle* h, bool carried) {
     const nmfkl_problem& pr = h->prob;
     // natural-order float64 column sums of W and F: sum over all cells of W^T F = sumW . sumF
     HIP_TRY(h, launch_permute_jobs(h->jobtab + kJobSumW, 1, h->sum_blocks, 0, nullptr, h->stream));
@@ -1090,6 +1117,12 @@ int objective_impl(nmfkl_handle* h, double* D_out, bool carried) {
     // one copy of [total, sums, error flags] into pinned memory
     HIP_TRY(h, hipMemcpyAsync(h->host_res, h->dres, results_words(pr.r) * sizeof(double), hipMemcpyDeviceToHost,
                               h->stream));
+    return NMFKL_OK;
+}
+
+// Waits for the copy and forms D from the results block.
+int objective_finish(nmfkl_handle* h, double* D_out) {
+    const nmfkl_problem& pr = h->prob;
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     unsigned derr = 0;
     std::memcpy(&derr, h->host_res + 1 + 2 * (size_t)pr.r, sizeof(unsigned));

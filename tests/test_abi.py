@@ -86,8 +86,12 @@ def test_create_rejects_bad_shapes_before_device_work():
 
 
 def test_null_handle_calls_fail_cleanly():
+    import ctypes
     lib = P.load()
     assert lib.nmfkl_sweep_F(None, 0) == -1
     assert lib.nmfkl_sweep_W(None, 0) == -1
     assert lib.nmfkl_invalidate_model(None) == -1
+    assert lib.nmfkl_objective_enqueue(None) == -1
+    d = ctypes.c_double()
+    assert lib.nmfkl_objective_read(None, ctypes.byref(d)) == -1
     assert lib.nmfkl_destroy(None) == -1

@@ -298,6 +298,32 @@ def test_carried_objective_and_refresh_mode():
         assert relf(W, Wo) <= 1e-4 and relf(F, Fo) <= 1e-4
 
 
+def test_objective_enqueue_then_read_equals_carried():
+    """The two-step objective gives the synchronous one's value bit for bit, only the last
+    enqueue is read, and a read without an enqueue is rejected."""
+    prob = CASES["corpus_mid"]()
+    Ds = {}
+    for mode in ("sync", "split"):
+        dev = P.upload(prob, "cuda")
+        h = P.nmfkl_create(dev, P.nmfkl_params_default())
+        D = []
+        for t in range(3):
+            P.nmfkl_sweep_F(h, t)
+            P.nmfkl_sweep_W(h, t)
+            if mode == "sync":
+                D.append(P.nmfkl_objective_carried(h))
+            else:
+                P.nmfkl_objective_enqueue(h)
+        if mode == "split":
+            D.append(P.nmfkl_objective_read(h))
+            with pytest.raises(P.NmfklError) as ei:
+                P.nmfkl_objective_read(h)
+            assert ei.value.code == -1
+        Ds[mode] = D
+        P.nmfkl_destroy(h)
+    assert Ds["split"][-1] == Ds["sync"][-1]
+
+
 def test_regularised_trajectory_parity():
     """eq. 2's L1/L2 terms (alpha_1, alpha_2, beta_1, beta_2 > 0): GPU vs oracle."""
     prob = CASES["corpus_mid"]()
