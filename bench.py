@@ -12,11 +12,14 @@ Prints one JSON line.  Besides the contract fields it carries:
   roofline      the dominant kernel's algorithmic (gather-model) bytes per launch over its
                 average HIP-event duration, against the 8 TB/s HBM peak; traffic from the
                 committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary when it was taken on the
-                current kernel source, else null;
+                current kernel source, else null; valu_busy_pct likewise from the committed
+                VALUBusy summary;
   cpu_baseline  the FP64 oracle timed on the host cores on a bounded sample (the first
                 sweeps of the same workload from the same initial factors);
+  sweep_ms      median, min and max of the timed sweeps (HIP events between steps);
   kernels       every timed launch group (ms per launch, GB/s under the gather model);
-  check         the GPU objective after the first sweeps vs the oracle's on the same sweeps;
+  check         the GPU objective after the first sweeps vs the oracle's on the same sweeps,
+                and the factors after them (relative Frobenius error);
   batched       64 independent planted problems (n ~ U{1k..20k}, m ~ U{1k..50k}, r in
                 {10, 16, 32, 64}, density 0.1-2%), 10 sweeps: one graph launch over the batch
                 (mapping picked by the batch autotuner) against the 64 problems run one after
@@ -31,6 +34,7 @@ import collections
 import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -63,12 +67,27 @@ def traffic_for(group: str):
     return entry.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(prob, seconds: float):
+def valu_busy_for(group: str):
+    """VALU-busy % of a launch group from the committed counter summary, if it matches the source."""
+    try:
+        with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "valu.json")) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != source_hash():
+        return None
+    return t.get("groups", {}).get(group)
+
+
+def cpu_baseline(prob, seconds: float, keep: int = 0):
+    """The oracle's sweeps for about `seconds`; also returns its objectives and its factors
+    after `keep` sweeps (for the GPU check)."""
     import numpy as np
     import oracle
     W = prob.W0.astype(np.float64)
     F = prob.F0.astype(np.float64)
     D = []
+    kept = None
     t0 = time.perf_counter()
     sweeps = 0
     while True:
@@ -77,6 +96,8 @@ def cpu_baseline(prob, seconds: float):
         W, _, _ = oracle.sweep_W(prob, F, W, ids)
         D.append(oracle.objective(prob, W, F))
         sweeps += 1
+        if sweeps == keep:
+            kept = (W.copy(), F.copy())
         if time.perf_counter() - t0 >= seconds or sweeps >= 60:
             break
     dt = time.perf_counter() - t0
@@ -92,7 +113,7 @@ def cpu_baseline(prob, seconds: float):
             "sample": f"{sweeps} full sweeps (F-half + W-half + objective) of the same corpus from "
                       f"the same initial factors, {dt:.1f} s wall",
             "single_core": {"value": prob.nnz * prob.r / d1, "unit": "updates/s", "cores": 1,
-                            "sample": f"the first F-half on one thread, {d1:.1f} s wall"}}, D
+                            "sample": f"the first F-half on one thread, {d1:.1f} s wall"}}, D, kept
 
 
 def sweep_leg(P, prob, args, log):
@@ -107,23 +128,29 @@ def sweep_leg(P, prob, args, log):
         P.nmfkl_sweep_W(h, t)
         D_warm.append(P.nmfkl_objective_carried(h))
     P.nmfkl_reset_timings(h)
+    warm_factors = (dev.W.cpu().numpy(), dev.F.cpu().numpy())
     log(f"[bench] warmup done, D = {D_warm}")
     torch.cuda.synchronize()
+    # one event per step on the handle's (default) stream: per-sweep times
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t_start = time.perf_counter()
+    evs[0].record()
     # each step: both halves and eq. 1 on the device; the objective's value is copied to pinned
     # host memory on the stream and read once at the end (no host round trip per step)
-    for t in range(args.warmup, args.warmup + args.steps):
+    for i, t in enumerate(range(args.warmup, args.warmup + args.steps)):
         P.nmfkl_sweep_F(h, t)
         P.nmfkl_sweep_W(h, t)
         P.nmfkl_objective_enqueue(h)
+        evs[i + 1].record()
     D = P.nmfkl_objective_read(h)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    sweep_ms = [evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)]
     tim = P.nmfkl_get_timings(h)
     P.nmfkl_destroy(h)
     del dev
     log(f"[bench] timed {args.steps} sweeps in {elapsed * 1e3:.2f} ms, final D = {D}")
-    return elapsed, tim, D_warm
+    return elapsed, tim, D_warm, sweep_ms, warm_factors
 
 
 def batched_leg(P, probs, log):
@@ -577,7 +604,7 @@ def main():
     import paper_1604_04026_amd as P
     torch.cuda.set_device(0)
 
-    elapsed, tim, D_warm = sweep_leg(P, prob, args, log)
+    elapsed, tim, D_warm, sweep_ms, warm_factors = sweep_leg(P, prob, args, log)
     updates = 2.0 * prob.nnz * prob.r * args.steps
     kernels = {}
     for name, k in tim.items():
@@ -595,7 +622,7 @@ def main():
     traffic = traffic_for(dom)
     roofline = {"bound": "hbm", "kernel": f"{dk['kernel']} ({dom})", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic,
+                "traffic": traffic, "valu_busy_pct": valu_busy_for(dom),
                 "bytes_model": "gather model: per nonzero 8 + 4r, per segment 8 + 8r"}
 
     out = {
@@ -618,6 +645,8 @@ def main():
                    "step": "sumW + F-half + sumF + W-half + float64 objective (eq. 1 from the "
                            "carried float64 model values)"},
         "roofline": roofline,
+        "sweep_ms": {"median": round(statistics.median(sweep_ms), 4), "min": round(min(sweep_ms), 4),
+                     "max": round(max(sweep_ms), 4), "source": "HIP events between steps on the handle's stream"},
         "kernels": kernels,
     }
     if batched is not None:
@@ -626,11 +655,17 @@ def main():
         W, arrivals, sptr, sidx, sval = serving
         out["serving"] = serving_leg(P, W, arrivals, sptr, sidx, sval, args.plain_window, log)
     if not args.no_cpu_baseline:
-        base, D_orc = cpu_baseline(prob, args.cpu_seconds)
+        base, D_orc, orc_factors = cpu_baseline(prob, args.cpu_seconds, keep=len(D_warm))
         out["cpu_baseline"] = base
         n_cmp = min(len(D_orc), len(D_warm))
         rel = [abs(D_warm[i] - D_orc[i]) / D_orc[i] for i in range(n_cmp)]
         out["check"] = {"sweeps_compared": n_cmp, "objective_rel_err_vs_oracle": [float(f"{x:.2e}") for x in rel]}
+        if orc_factors is not None and n_cmp == len(D_warm):
+            import numpy as np
+            fe = {}
+            for name, g, o in (("W", warm_factors[0], orc_factors[0]), ("F", warm_factors[1], orc_factors[1])):
+                fe[name] = float(f"{np.linalg.norm(g.astype(np.float64) - o) / np.linalg.norm(o):.2e}")
+            out["check"]["factor_rel_err_vs_oracle"] = fe
     print(json.dumps(out), flush=True)
 
 
