@@ -250,8 +250,9 @@ void free_plan(BinPlan* p) {
 // Largest B that a segment of the cooperative queue may have.  In the queue the blocks that
 // take the first parts of a segment wait until its last part is taken; on the corpus (B <= 20)
 // the queue beats launches per pack of segments (long_W 1.28 vs 1.54 ms), on the large corpus
-// (B up to 387) the segments of more than 32 blocks run faster in packs.
-constexpr int kQueueMaxB = 32;
+// (B up to 387) the segments of more than 20 blocks run faster in packs (long_W 128 ms with
+// this bound, 131 ms with 32, 133 ms with everything queued; 12 costs the corpus 0.06 ms).
+constexpr int kQueueMaxB = 20;
 
 int plan_bins(const std::vector<SegSource>& src, int long_capacity, int single_capacity, int bin_shift,
               bool problem_major, BinPlan* plan, std::string* err) {
