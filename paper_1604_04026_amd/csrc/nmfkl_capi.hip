@@ -105,7 +105,7 @@ struct nmfkl_handle {
     SweepArgs* argtab = nullptr;       // device: kNumArgs sweep-argument entries
     PermJob* jobtab = nullptr;         // device: kNumJobs permute jobs
     // timing (params.collect_timings): event pairs per launch group, resolved on demand
-    struct Pending { int kind; hipEvent_t a, b; };
+    struct Pending { int kind; hipEvent_t a, b; bool shared_a; };  // shared_a: a is the previous record's b
     std::vector<Pending> pending;
     std::vector<hipEvent_t> event_pool;
     nmfkl_timings timings{};
@@ -167,7 +167,7 @@ hipError_t take_event(nmfkl_handle* h, hipEvent_t* ev) {
 // Starts a timed launch group; returns the index of the pending record or -1 when off.
 int timer_begin(nmfkl_handle* h, int kind) {
     if (!h->prm.collect_timings) return -1;
-    nmfkl_handle::Pending p{kind, nullptr, nullptr};
+    nmfkl_handle::Pending p{kind, nullptr, nullptr, false};
     if (take_event(h, &p.a) != hipSuccess || take_event(h, &p.b) != hipSuccess) return -1;
     if (hipEventRecord(p.a, h->stream) != hipSuccess) return -1;
     h->pending.push_back(p);
@@ -177,6 +177,17 @@ int timer_begin(nmfkl_handle* h, int kind) {
 void timer_end(nmfkl_handle* h, int idx) {
     if (idx < 0) return;
     (void)hipEventRecord(h->pending[idx].b, h->stream);
+}
+
+// Ends timed group prev (if any) and starts one of `kind` with the same event, for groups
+// that follow each other on the stream.
+int timer_switch(nmfkl_handle* h, int prev, int kind) {
+    if (prev < 0) return timer_begin(h, kind);
+    if (hipEventRecord(h->pending[prev].b, h->stream) != hipSuccess) return -1;
+    nmfkl_handle::Pending p{kind, h->pending[prev].b, nullptr, true};
+    if (take_event(h, &p.b) != hipSuccess) return -1;
+    h->pending.push_back(p);
+    return (int)h->pending.size() - 1;
 }
 
 hipError_t resolve_timings(nmfkl_handle* h) {
@@ -189,7 +200,7 @@ hipError_t resolve_timings(nmfkl_handle* h) {
             h->timings.k[p.kind].ms_total += ms;
             h->timings.k[p.kind].launches += 1;
         }
-        h->event_pool.push_back(p.a);
+        if (!p.shared_a) h->event_pool.push_back(p.a);
         h->event_pool.push_back(p.b);
     }
     h->pending.clear();
@@ -197,7 +208,10 @@ hipError_t resolve_timings(nmfkl_handle* h) {
 }
 
 void release(nmfkl_handle* h) {
-    for (auto& p : h->pending) { h->event_pool.push_back(p.a); h->event_pool.push_back(p.b); }
+    for (auto& p : h->pending) {
+        if (!p.shared_a) h->event_pool.push_back(p.a);
+        h->event_pool.push_back(p.b);
+    }
     h->pending.clear();
     for (hipEvent_t ev : h->event_pool) (void)hipEventDestroy(ev);
     h->event_pool.clear();
@@ -517,19 +531,23 @@ int refresh_model(nmfkl_handle* h) {
 // over the plan, with the argument table tab; timed: bracket them with the handle's timers.
 hipError_t enqueue_plan(const BinPlan& plan, const SweepArgs* tab, unsigned long long* coop_words,
                         unsigned* dev_err, bool cooperative, bool lookahead, hipStream_t s,
-                        nmfkl_handle* timed, int long_kind, int fused_kind) {
+                        nmfkl_handle* timed, int long_kind, int fused_kind, int open_timer = -1) {
     hipError_t e;
     const bool any_long = plan.single_blocks > 0 || !plan.rounds.empty();
-    const int tl = (timed && any_long) ? timer_begin(timed, long_kind) : -1;
+    // timed groups follow each other: each one's start event ends the group before it
+    // (open_timer: a group the caller started just before)
+    int prev = open_timer;
+    const int tl = (timed && any_long) ? timer_switch(timed, prev, long_kind) : -1;
+    if (tl >= 0) prev = tl;
     if ((e = launch_sweep_long_single(tab, plan.long_work, plan.single_blocks, s)) != hipSuccess) return e;
     for (const auto& rd : plan.rounds)
         if ((e = launch_sweep_long(tab, plan.long_work + rd.first, rd.nblocks, rd.grid, coop_words, rd.ngroups,
                                    dev_err, rd.pmax, cooperative, s)) != hipSuccess)
             return e;
-    if (timed) timer_end(timed, tl);
-    const int tf = (timed && plan.nblocks) ? timer_begin(timed, fused_kind) : -1;
+    const int tf = (timed && plan.nblocks) ? timer_switch(timed, prev, fused_kind) : -1;
+    if (tf >= 0) prev = tf;
     if ((e = launch_sweep_fused(tab, plan.work, plan.segs, plan.nblocks, lookahead, s)) != hipSuccess) return e;
-    if (timed) timer_end(timed, tf);
+    if (timed) timer_end(timed, prev);
     return hipSuccess;
 }
 
@@ -608,13 +626,12 @@ int half_sweep(nmfkl_handle* h, int32_t t, bool fhalf) {
     const PermJob* job = h->jobtab + (fhalf ? kJobF : kJobW);
     HIP_TRY(h, launch_permute_jobs(job, 1, h->sum_blocks, t, nullptr, h->stream));
     HIP_TRY(h, launch_finalize_jobs(job, 1, pr.r, h->stream));
-    timer_end(h, ts);
     int ai;
     if (fhalf) ai = (h->model == kModelCsc || h->model == kModelCscFresh) ? kArgFfromCsc : kArgFfromCsr;
     else ai = h->model == kModelCsr ? kArgWfromCsr : kArgWfromCsc;
     HIP_TRY(h, enqueue_plan(plan, h->argtab + ai, h->coop_words, h->dev_err, true,
                             (h->prm.tuning & 1) != 0, h->stream, h,
-                            fhalf ? NMFKL_T_LONG_F : NMFKL_T_LONG_W, fhalf ? NMFKL_T_FUSED_F : NMFKL_T_FUSED_W));
+                            fhalf ? NMFKL_T_LONG_F : NMFKL_T_LONG_W, fhalf ? NMFKL_T_FUSED_F : NMFKL_T_FUSED_W, ts));
     h->model = fhalf ? kModelCsc : kModelCsr;
     return NMFKL_OK;
 }
