@@ -507,10 +507,16 @@ void make_jobs(nmfkl_handle* h, PermJob (&jobs)[kNumJobs]) {
             j.identity = 0;
             j.bf16 = h->prm.tile_bf16;
         } else {
+            // the objective's two jobs run in one launch: SumF after SumW, with partials of its own
             j.Ap = nullptr;
             j.sums = h->sums2 + (k == kJobSumW ? 0 : pr.r);
             j.ids = nullptr;
             j.identity = 1;
+            if (k == kJobSumF) {
+                j.first_block = h->sum_blocks;
+                j.first_sum = pr.r;
+                j.partials = h->partials + (size_t)h->sum_blocks * pr.r;
+            }
         }
         jobs[k] = j;
     }
@@ -802,7 +808,7 @@ int create_ooc(const nmfkl_problem& pr, const nmfkl_params& prm, void* hip_strea
     OOC_HIP(dalloc(&h->Ap, (size_t)Pmax * h->Sp));
     OOC_HIP(dalloc(&h->sumA, NMFKL_R_MAX));
     h->sum_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, Pmax / 64));
-    OOC_HIP(dalloc(&h->partials, (size_t)h->sum_blocks * pr.r));
+    OOC_HIP(dalloc(&h->partials, 2 * (size_t)h->sum_blocks * pr.r));
     OOC_HIP(dalloc(&h->ids, NMFKL_R_MAX));
     h->obj_blocks = 4096;
     OOC_HIP(dalloc(&h->obj_partials, h->obj_blocks));
@@ -975,7 +981,7 @@ int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_str
     CREATE_HIP(dalloc(&h->Ap, (size_t)Pmax * h->Sp));
     CREATE_HIP(dalloc(&h->sumA, NMFKL_R_MAX));
     h->sum_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, Pmax / 64));
-    CREATE_HIP(dalloc(&h->partials, (size_t)h->sum_blocks * pr.r));
+    CREATE_HIP(dalloc(&h->partials, 2 * (size_t)h->sum_blocks * pr.r));
     CREATE_HIP(dalloc(&h->ids, NMFKL_R_MAX));
     CREATE_HIP(dalloc(&h->Mcsc, nnz));
     CREATE_HIP(dalloc(&h->Mcsr, nnz));
@@ -1101,10 +1107,9 @@ int objective_impl(nmfkl_handle* h, double* D_out, bool carried) {
 int objective_enqueue(nmfkl_handle* h, bool carried) {
     const nmfkl_problem& pr = h->prob;
     // natural-order float64 column sums of W and F: sum over all cells of W^T F = sumW . sumF
-    HIP_TRY(h, launch_permute_jobs(h->jobtab + kJobSumW, 1, h->sum_blocks, 0, nullptr, h->stream));
-    HIP_TRY(h, launch_finalize_jobs(h->jobtab + kJobSumW, 1, pr.r, h->stream));
-    HIP_TRY(h, launch_permute_jobs(h->jobtab + kJobSumF, 1, h->sum_blocks, 0, nullptr, h->stream));
-    HIP_TRY(h, launch_finalize_jobs(h->jobtab + kJobSumF, 1, pr.r, h->stream));
+    // both jobs (adjacent in the table) in one permute and one finalize launch
+    HIP_TRY(h, launch_permute_jobs(h->jobtab + kJobSumW, 2, 2 * h->sum_blocks, 0, nullptr, h->stream));
+    HIP_TRY(h, launch_finalize_jobs(h->jobtab + kJobSumW, 2, 2 * pr.r, h->stream));
     if (h->ooc) {
         // eq. 1 streamed: each column chunk's model values and terms (no model values kept)
         const int tm = timer_begin(h, NMFKL_T_MODEL);
