@@ -50,8 +50,15 @@ KERNEL_NAMES = {"fused_F": "k_sweep_fused", "fused_W": "k_sweep_fused", "long_F"
 
 
 def source_hash() -> str:
-    with open(KERNEL_SOURCE, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """Hash of the kernel source with comments and whitespace runs removed, so that counter
+    summaries stay matched across comment edits and are dropped on any code change."""
+    import re
+    with open(KERNEL_SOURCE, encoding="utf-8") as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    text = " ".join(text.split())
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
 def traffic_for(group: str):

@@ -533,7 +533,7 @@ int refresh_model(nmfkl_handle* h) {
     return NMFKL_OK;
 }
 
-// Enqueues one half-sweep's sweep launches (long single-block, cooperative rounds, fused)
+// Enqueues one half-sweep's sweep launches (long single-block, cooperative, fused)
 // over the plan, with the argument table tab; timed: bracket them with the handle's timers.
 hipError_t enqueue_plan(const BinPlan& plan, const SweepArgs* tab, unsigned long long* coop_words,
                         unsigned* dev_err, bool cooperative, bool lookahead, hipStream_t s,
@@ -1265,7 +1265,7 @@ void batch_release(nmfkl_batch* b) {
 }
 
 // Bins of both halves over all problems under b->prm.bin_shift, and cross-block scratch for
-// their cooperative rounds.
+// their cooperative launches.
 int batch_plan(nmfkl_batch* b) {
     drop_graphs(b);
     free_plan(&b->plan[0]);

@@ -154,14 +154,14 @@ constexpr Variant kVariants[kNumVariants] = {{8, 4}, {16, 4}, {32, 4}, {64, 4}, 
 constexpr int kFusedThreads = 256;
 constexpr int kMaxFusedLength = 1024;   // 256 * 4
 
-// Longer segments: blocks of kLongThreads threads, kLongE nonzeros per thread; a segment
-// spans B = ceil(L / kLongCapacity) cooperating blocks.
+// Longer segments of at most kLongCapacity nonzeros: one block of kLongThreads threads with
+// kLongE nonzeros per thread.
 constexpr int kLongThreads = 256;
 constexpr int kLongE = 8;
 constexpr int kLongCapacity = kLongThreads * kLongE;
 // Segments longer than kLongCapacity: blocks of kCoopE nonzeros per thread (two blocks per
-// compute unit; more nonzeros per unit than three blocks of kLongE, so fewer cooperative
-// rounds), B = ceil(L / kCoopCapacity) of them per segment.
+// compute unit; more nonzeros per unit than three blocks of kLongE), B = ceil(L /
+// kCoopCapacity) of them per segment.
 constexpr int kCoopE = 20;
 constexpr int kCoopCapacity = kLongThreads * kCoopE;
 

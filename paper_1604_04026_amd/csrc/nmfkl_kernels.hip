@@ -856,15 +856,14 @@ hipError_t launch_sweep_fused(const SweepArgs* tab, const BlockWork* work, const
     return hipGetLastError();
 }
 
-// Long segments: kLongThreads threads x kLongE nonzeros per block, lookahead form.  A
-// segment of L nonzeros takes B = ceil(L / kLongCapacity) blocks.  COOP = false: one block
-// per segment (B = 1), ordinary launch.  COOP = true: the blocks of a segment cooperate
-// through CoopReducer; all blocks of the launch are co-resident (cooperative launch), so
-// every wait ends.  Counts and ids live in LDS, the model values in registers, w and u are
-// recomputed from the model at each chunk start, and tile chunks are 4 coordinates wide.
-// Single-block segments (COOP = false) use kLongE = 8 nonzeros per thread within 168
-// registers (3 blocks per compute unit); cooperative segments use kCoopE = 20 (2 blocks per
-// compute unit, 10240 nonzeros per unit: fewer rounds than 3 blocks of 2048).
+// Long segments, lookahead form.  Segments of at most kLongCapacity nonzeros take one block
+// of kLongThreads threads x kLongE nonzeros (COOP = false, ordinary launch; 3 blocks per
+// compute unit within 168 registers).  Longer ones take B = ceil(L / kCoopCapacity) blocks of
+// kCoopE = 20 nonzeros per thread (COOP = true: 2 blocks per compute unit, 10240 nonzeros
+// per unit, more than 3 blocks of 2048) that cooperate through CoopReducer; all blocks of
+// such a launch are co-resident (cooperative launch), so every wait ends.  Counts and ids
+// live in LDS, the model values in registers, w and u are recomputed from the model at each
+// chunk start, and tile chunks are 4 coordinates wide.
 constexpr int kLongCW = 4;
 constexpr int kCoopCW = 4;
 
