@@ -151,16 +151,30 @@ __global__ void __launch_bounds__(256) k_permute_jobs(const PermJob* __restrict_
         const int k = s < Sp ? sid[s] : -1;
         double acc = 0.0;
         if (s < Sp) {
-            for (int64_t p = p0 + ry; p < p1; p += 4) {
-                float a = k >= 0 ? jb.A[p * r + k] : 0.0f;
-                if (jb.bf16) {
-                    const uint16_t q = bf16_rne(a);
-                    a = bf16_to_float(q);
-                    if (jb.Ap) reinterpret_cast<uint16_t*>(jb.Ap)[p * Sp + s] = q;
-                } else if (jb.Ap) {
-                    jb.Ap[p * Sp + s] = a;
+            // rows ry, ry + 4, ...: U loads issued before their stores (the copy may not alias
+            // the factor), then added in row order
+            constexpr int U = 4;
+            const float* __restrict__ A = jb.A;
+            for (int64_t pb = p0 + ry; pb < p1; pb += 4 * U) {
+                float a[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t p = pb + 4 * u;
+                    a[u] = (k >= 0 && p < p1) ? A[p * r + k] : 0.0f;
                 }
-                acc += (double)a;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t p = pb + 4 * u;
+                    if (p >= p1) break;
+                    if (jb.bf16) {
+                        const uint16_t q = bf16_rne(a[u]);
+                        a[u] = bf16_to_float(q);
+                        if (jb.Ap) reinterpret_cast<uint16_t*>(jb.Ap)[p * Sp + s] = q;
+                    } else if (jb.Ap) {
+                        jb.Ap[p * Sp + s] = a[u];
+                    }
+                    acc += (double)a[u];
+                }
             }
         }
         red[ry][cx] = acc;
@@ -173,10 +187,11 @@ __global__ void __launch_bounds__(256) k_permute_jobs(const PermJob* __restrict_
         // the chunk-major copy: thread (row group, component q) writes 16 consecutive rows'
         // 16-byte chunk entries per wave, so the stores are contiguous
         const int q = threadIdx.x & 3;
+        const float* __restrict__ A = jb.A;
         for (int c = 0; c < Sc / 4; ++c) {
             const int k = sid[4 * c + q];
             for (int64_t p = p0 + (threadIdx.x >> 2); p < p1; p += 64) {
-                const float a = k >= 0 ? jb.A[p * r + k] : 0.0f;
+                const float a = k >= 0 ? A[p * r + k] : 0.0f;
                 const int64_t pc = ((int64_t)c * jb.P + p) * 4 + q;
                 if (jb.bf16) reinterpret_cast<uint16_t*>(jb.Apc)[pc] = bf16_rne(a);
                 else jb.Apc[pc] = a;
