@@ -425,3 +425,42 @@ def test_huge_row_matches_the_oracle():
     e = relf(Wg, Wo)
     print(f"huge row W-half: rel {e:.2e}; rows {Wg.tolist()}")
     assert e <= 1e-4
+
+
+def boundary_rows_problem(r=6, seed=0):
+    """Rows whose lengths sit on both sides of every length boundary of the W-half's launches:
+    the binned variants (32, 64, 128, 256, 512, 1024), the single-block kernel (2048), one
+    cooperative block (5120) and the queue bound (20 blocks = 102,400), plus 800 rows of
+    1025..2048 nonzeros (more than one wave of the single-block kernel on a 256-CU device)."""
+    g = np.random.default_rng(seed)
+    edges = [32, 64, 128, 256, 512, 1024, 2048, 5120, 20 * 5120]
+    lengths = [L for e in edges for L in (e, e + 1)] + list(g.integers(1025, 2049, 800))
+    n, m = len(lengths), 20 * 5120 + 1
+    rows = np.concatenate([np.full(L, i, np.int64) for i, L in enumerate(lengths)])
+    cols = np.concatenate([g.choice(m, L, replace=False) for L in lengths])
+    order = np.lexsort((rows, cols))
+    rows, cols = rows[order], cols[order]
+    ptr = np.zeros(m + 1, np.int64)
+    np.cumsum(np.bincount(cols, minlength=m), out=ptr[1:])
+    val = g.geometric(0.6, rows.size).astype(np.float32)
+    return workloads._problem(n, m, r, ptr, rows.astype(np.int32), val, seed, 12, {"name": "boundary rows"})
+
+
+def test_every_length_boundary_matches_the_oracle():
+    prob = boundary_rows_problem()
+    lens = np.diff(prob.csr_ptr)
+    assert lens.max() == 20 * 5120 + 1 and ((lens > 1024) & (lens <= 2048)).sum() > 768
+    t = 1
+    ids = oracle.permutation(0, t, 0, prob.r)
+    Wo, _, _ = oracle.sweep_W(prob, prob.F0.astype(np.float64), prob.W0.astype(np.float64), ids)
+    Wg = gpu_half(prob, prob.W0, prob.F0, t, "W")
+    Fo, _, _ = oracle.sweep_F(prob, prob.W0.astype(np.float64), prob.F0.astype(np.float64), ids)
+    Fg = gpu_half(prob, prob.W0, prob.F0, t, "F")
+    # each boundary row on its own (the 800 extra rows would hide one wrong row in the norm)
+    err = np.linalg.norm(Wg - Wo, axis=1)
+    norm = np.linalg.norm(Wo, axis=1)
+    nb = 18
+    worst = float(np.max(err[:nb] / (norm[:nb] + 1e-5 * norm.max())))
+    print(f"boundary rows: W rel {relf(Wg, Wo):.2e} (worst boundary row {worst:.2e}), F rel {relf(Fg, Fo):.2e}")
+    assert relf(Wg, Wo) <= 1e-4 and relf(Fg, Fo) <= 1e-4
+    assert worst <= 1e-3
