@@ -464,3 +464,34 @@ def test_every_length_boundary_matches_the_oracle():
     print(f"boundary rows: W rel {relf(Wg, Wo):.2e} (worst boundary row {worst:.2e}), F rel {relf(Fg, Fo):.2e}")
     assert relf(Wg, Wo) <= 1e-4 and relf(Fg, Fo) <= 1e-4
     assert worst <= 1e-3
+
+
+def test_queue_of_many_long_rows_matches_the_oracle():
+    """300 rows of 8,000-11,000 nonzeros (2-3 cooperating blocks each): more parts than the
+    device holds at once, so blocks take parts from the ticket queue as others finish."""
+    g = np.random.default_rng(3)
+    n, m, r = 300, 24000, 4
+    lengths = g.integers(8000, 11001, n)
+    rows = np.concatenate([np.full(L, i, np.int64) for i, L in enumerate(lengths)])
+    cols = np.concatenate([g.choice(m, L, replace=False) for L in lengths])
+    order = np.lexsort((rows, cols))
+    rows, cols = rows[order], cols[order]
+    ptr = np.zeros(m + 1, np.int64)
+    np.cumsum(np.bincount(cols, minlength=m), out=ptr[1:])
+    val = g.geometric(0.6, rows.size).astype(np.float32)
+    prob = workloads._problem(n, m, r, ptr, rows.astype(np.int32), val, 3, 13, {"name": "queue rows"})
+    parts = int(np.sum((lengths + 5119) // 5120))
+    assert parts > 2 * 256
+    W, F = prob.W0.astype(np.float64), prob.F0.astype(np.float64)
+    dev = P.upload(prob, "cuda")
+    h = P.nmfkl_create(dev, P.nmfkl_params_default())
+    for t in range(2):
+        ids = oracle.permutation(0, t, 0, r)
+        F, _, _ = oracle.sweep_F(prob, W, F, ids)
+        W, _, _ = oracle.sweep_W(prob, F, W, ids)
+        P.nmfkl_sweep_F(h, t)
+        P.nmfkl_sweep_W(h, t)
+    Wg, Fg = dev.W.cpu().numpy(), dev.F.cpu().numpy()
+    P.nmfkl_destroy(h)
+    print(f"queue rows ({parts} parts): W rel {relf(Wg, W):.2e}, F rel {relf(Fg, F):.2e}")
+    assert relf(Wg, W) <= 1e-4 and relf(Fg, F) <= 1e-4
