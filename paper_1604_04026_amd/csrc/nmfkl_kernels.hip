@@ -543,8 +543,11 @@ __device__ __forceinline__ void newton_coordinate(const SweepArgs& a, int s, con
             d = fmaxf(xn, 0.0f) - xk;
         }
         const float dN = d;  // Alg. 2's projected Newton step (the break test uses it)
-        double mm[E];
-        float wn[E], un[E];
+        // the trials write the lane state in place; the model before the step is kept for
+        // a halved retry and for the restore after a rejection
+        double axo[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) axo[e] = st.ax[e];
         float acc[NACC];
         double gn, Pn;
         float hn;
@@ -556,13 +559,12 @@ __device__ __forceinline__ void newton_coordinate(const SweepArgs& a, int s, con
             const double dd = (double)d;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                const double m = fmax(fma(dd, (double)tk[e], st.ax[e]), 0.0);
+                const double m = fmax(fma(dd, (double)tk[e], axo[e]), 0.0);
                 const float ri = fast_rcp((float)m + a.eps_log);
                 const float ww = st.v(e) * ri;
                 const float uu = ww * ri;
-                mm[e] = m;
-                wn[e] = ww;
-                un[e] = uu;
+                st.ax[e] = m;
+                st.set_wu(e, ww, uu);
                 acc[OFF] = fmaf(tk[e], ww, acc[OFF]);
                 acc[OFF + 1] = fmaf(tk[e], tk[e] * uu, acc[OFF + 1]);
                 later(e, ww, uu, acc);
@@ -579,11 +581,17 @@ __device__ __forceinline__ void newton_coordinate(const SweepArgs& a, int s, con
             ++j;
             cnt[3] += 1;
         }
-        if (rejected) { cnt[4] += 1; break; }
+        if (rejected) {
+            // back to the model before the step; w and u by the formula that made them
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            st.ax[e] = mm[e];
-            st.set_wu(e, wn[e], un[e]);
+            for (int e = 0; e < E; ++e) {
+                st.ax[e] = axo[e];
+                const float ri = fast_rcp((float)axo[e] + a.eps_log);
+                const float ww = st.v(e) * ri;
+                st.set_wu(e, ww, ww * ri);
+            }
+            cnt[4] += 1;
+            break;
         }
         commit(acc);
         const float xprev = xk;
