@@ -535,8 +535,9 @@ int refresh_model(nmfkl_handle* h) {
 
 // Enqueues one half-sweep's sweep launches (long single-block, cooperative, fused)
 // over the plan, with the argument table tab; timed: bracket them with the handle's timers.
+// stats: some entry of tab collects statistics.
 hipError_t enqueue_plan(const BinPlan& plan, const SweepArgs* tab, unsigned long long* coop_words,
-                        unsigned* dev_err, bool cooperative, bool lookahead, hipStream_t s,
+                        unsigned* dev_err, bool cooperative, bool lookahead, bool stats, hipStream_t s,
                         nmfkl_handle* timed, int long_kind, int fused_kind, int open_timer = -1) {
     hipError_t e;
     const bool any_long = plan.single_blocks > 0 || !plan.rounds.empty();
@@ -552,7 +553,7 @@ hipError_t enqueue_plan(const BinPlan& plan, const SweepArgs* tab, unsigned long
             return e;
     const int tf = (timed && plan.nblocks) ? timer_switch(timed, prev, fused_kind) : -1;
     if (tf >= 0) prev = tf;
-    if ((e = launch_sweep_fused(tab, plan.work, plan.segs, plan.nblocks, lookahead, s)) != hipSuccess) return e;
+    if ((e = launch_sweep_fused(tab, plan.work, plan.segs, plan.nblocks, lookahead, stats, s)) != hipSuccess) return e;
     if (timed) timer_end(timed, prev);
     return hipSuccess;
 }
@@ -602,7 +603,7 @@ int half_sweep_ooc(nmfkl_handle* h, int32_t t, bool fhalf) {
     for (size_t c = 0; c < h->chunks[half].size(); ++c) {
         HIP_TRY(h, ooc_stage(h, half, c));
         HIP_TRY(h, enqueue_plan(h->chunks[half][c].plan, h->ooc_args + first + c, h->coop_words, h->dev_err, true,
-                                (h->prm.tuning & 1) != 0, h->stream, h, fhalf ? NMFKL_T_LONG_F : NMFKL_T_LONG_W,
+                                (h->prm.tuning & 1) != 0, h->prm.collect_stats != 0, h->stream, h, fhalf ? NMFKL_T_LONG_F : NMFKL_T_LONG_W,
                                 fhalf ? NMFKL_T_FUSED_F : NMFKL_T_FUSED_W));
         HIP_TRY(h, ooc_release(h, c));
     }
@@ -636,7 +637,7 @@ int half_sweep(nmfkl_handle* h, int32_t t, bool fhalf) {
     if (fhalf) ai = (h->model == kModelCsc || h->model == kModelCscFresh) ? kArgFfromCsc : kArgFfromCsr;
     else ai = h->model == kModelCsr ? kArgWfromCsr : kArgWfromCsc;
     HIP_TRY(h, enqueue_plan(plan, h->argtab + ai, h->coop_words, h->dev_err, true,
-                            (h->prm.tuning & 1) != 0, h->stream, h,
+                            (h->prm.tuning & 1) != 0, h->prm.collect_stats != 0, h->stream, h,
                             fhalf ? NMFKL_T_LONG_F : NMFKL_T_LONG_W, fhalf ? NMFKL_T_FUSED_F : NMFKL_T_FUSED_W, ts));
     h->model = fhalf ? kModelCsc : kModelCsr;
     return NMFKL_OK;
@@ -1319,7 +1320,7 @@ hipError_t batch_enqueue(nmfkl_batch* b, hipStream_t s, int nsweeps, bool cooper
             if ((e = launch_permute_jobs(jobs, np, b->perm_blocks[half], k, b->t_dev, s)) != hipSuccess) return e;
             if ((e = launch_finalize_jobs(jobs, np, b->nsum[half], s)) != hipSuccess) return e;
             if ((e = enqueue_plan(b->plan[half], b->argtab + (size_t)half * np, b->coop_words,
-                                  b->dev_err, cooperative, la, s, nullptr, 0, 0)) != hipSuccess)
+                                  b->dev_err, cooperative, la, true, s, nullptr, 0, 0)) != hipSuccess)
                 return e;
         }
     return hipSuccess;

@@ -184,9 +184,10 @@ hipError_t launch_permute_jobs(const PermJob* jobs, int njobs, int nblocks, int6
 hipError_t launch_finalize_jobs(const PermJob* jobs, int njobs, int nsum, hipStream_t stream);
 hipError_t launch_model_terms(const double* M, const float* val, int64_t nnz, double* partials,
                               int nblocks, hipStream_t stream);
-// tab: device table of SweepArgs; each block uses tab[work.prob].
+// tab: device table of SweepArgs; each block uses tab[work.prob].  stats: false when no
+// entry of the table collects statistics (the launch then keeps no counters).
 hipError_t launch_sweep_fused(const SweepArgs* tab, const BlockWork* work, const int32_t* segs,
-                              int nblocks, bool lookahead, hipStream_t stream);
+                              int nblocks, bool lookahead, bool stats, hipStream_t stream);
 // Long segments that fit one block (B = 1): ordinary launch.
 hipError_t launch_sweep_long_single(const SweepArgs* tab, const LongWork* work, int nblocks,
                                     hipStream_t stream);

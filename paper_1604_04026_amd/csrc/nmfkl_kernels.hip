@@ -517,21 +517,34 @@ __device__ __forceinline__ float comp(const float4 (&t)[E][kQuads<CW>], int e, i
 }
 
 // Alg. 2's inner loop for coordinate s of one segment, given the lane's fixed-factor values
+// Per-lane statistics (coordinates, evaluations, accepted steps, halvings, rejections,
+// step-limit exits).  Counters<false> compiles them away for launches that do not collect
+// them: six registers fewer in a kernel bounded by 128.
+template <bool ON>
+struct Counters {
+    unsigned c[6] = {0, 0, 0, 0, 0, 0};
+    __device__ __forceinline__ void add(int q) { c[q] += 1; }
+};
+template <>
+struct Counters<false> {
+    __device__ __forceinline__ void add(int) {}
+};
+
 // tk[e] for this coordinate and eq. 6's sums S1, S2 at the current model.  A trial keeps NACC
 // float sums with the coordinate's own S1, S2 at acc[OFF], acc[OFF + 1]; later(e, ww, uu, acc)
 // adds further sums per element (the lookahead form adds those of the chunk's later
 // coordinates) and red.sum(acc, OFF) all-reduces acc[OFF..NACC); commit(acc) runs when a
 // trial is accepted.
-template <int E, int NACC, int OFF, class Later, class Commit, class Red, class St>
+template <int E, int NACC, int OFF, class Later, class Commit, class Red, class St, class Cnt>
 __device__ __forceinline__ void newton_coordinate(const SweepArgs& a, int s, const float (&tk)[E], float S1,
                                                   float S2, Later&& later, Commit&& commit, St& st, float* xs,
-                                                  Red& red, unsigned (&cnt)[6]) {
+                                                  Red& red, Cnt& cnt) {
     float xk = xs[s];
     const double sA = a.sumA[s];
     double P = sA + (double)a.alpha * xk + (double)a.beta;
     double g = P - (double)S1;
     float h = S2 + a.alpha;
-    cnt[0] += 1;
+    cnt.add(0);
     int steps = 0;
     while ((g < -(double)a.eps_g * P) || (g > (double)a.eps_g * P && xk > 0.0f)) {
         float d;
@@ -570,7 +583,7 @@ __device__ __forceinline__ void newton_coordinate(const SweepArgs& a, int s, con
                 later(e, ww, uu, acc);
             }
             red.sum(acc, OFF);
-            cnt[1] += 1;
+            cnt.add(1);
             const float xt = xk + d;
             Pn = sA + (double)a.alpha * xt + (double)a.beta;
             gn = Pn - (double)acc[OFF];
@@ -579,7 +592,7 @@ __device__ __forceinline__ void newton_coordinate(const SweepArgs& a, int s, con
             if (j == a.j_max) { rejected = true; break; }
             d *= 0.5f;
             ++j;
-            cnt[3] += 1;
+            cnt.add(3);
         }
         if (rejected) {
             // back to the model before the step; w and u by the formula that made them
@@ -590,7 +603,7 @@ __device__ __forceinline__ void newton_coordinate(const SweepArgs& a, int s, con
                 const float ww = st.v(e) * ri;
                 st.set_wu(e, ww, ww * ri);
             }
-            cnt[4] += 1;
+            cnt.add(4);
             break;
         }
         commit(acc);
@@ -600,18 +613,18 @@ __device__ __forceinline__ void newton_coordinate(const SweepArgs& a, int s, con
         h = hn;
         P = Pn;
         ++steps;
-        cnt[2] += 1;
+        cnt.add(2);
         const bool stop = a.literal_break ? (dN < a.eps_x * xprev) : (fabsf(dN) < a.eps_x * xprev);
         if (stop) break;
-        if (steps >= a.t_max) { cnt[5] += 1; break; }
+        if (steps >= a.t_max) { cnt.add(5); break; }
     }
     xs[s] = xk;
 }
 
 // eq. 6's sums of one coordinate at the current model, all-reduced over the segment.
-template <int E, class Red, class St>
+template <int E, class Red, class St, class Cnt>
 __device__ __forceinline__ void coordinate_sums(const SweepArgs& a, const float (&tk)[E], St& st, Red& red,
-                                                float& S1, float& S2, unsigned (&cnt)[6]) {
+                                                float& S1, float& S2, Cnt& cnt) {
     float acc[2] = {0.0f, 0.0f};
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -623,7 +636,7 @@ __device__ __forceinline__ void coordinate_sums(const SweepArgs& a, const float 
     red.sum(acc, 0);
     S1 = acc[0];
     S2 = acc[1];
-    cnt[1] += 1;
+    cnt.add(1);
 }
 
 // Coordinate s = c*CW + cc with the chunk's tile values in registers.  LA (lookahead):
@@ -632,10 +645,10 @@ __device__ __forceinline__ void coordinate_sums(const SweepArgs& a, const float 
 // trial model, so that an accepted step leaves LS valid.  The sums are the same numbers the
 // sequential order would compute later from the same model.  Without LA, the coordinate's
 // own sums are evaluated here.
-template <int cc, int E, bool LA, int CW, class Red, class St>
+template <int cc, int E, bool LA, int CW, class Red, class St, class Cnt>
 __device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s,
                                                 const float4 (&t)[E][kQuads<CW>], St& st, float* xs,
-                                                Red& red, float (&LS)[2 * CW], unsigned (&cnt)[6]) {
+                                                Red& red, float (&LS)[2 * CW], Cnt& cnt) {
     float tk[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) tk[e] = comp<E, CW>(t, e, cc);
@@ -668,10 +681,10 @@ __device__ __forceinline__ void coordinate_step(const SweepArgs& a, int s,
 // compile-time constant, so every register array is indexed statically).
 // cmap (fold-in): x and sumA are kept in the original coordinate order and step s of the
 // pass visits coordinate cmap[s]; null: they are already in the sweep's order.
-template <int CC, int E, bool LA, int CW, class Red, class St>
+template <int CC, int E, bool LA, int CW, class Red, class St, class Cnt>
 __device__ __forceinline__ void chunk_steps(const SweepArgs& a, int c, const float4 (&t)[E][kQuads<CW>],
                                             St& st, float* xs, Red& red, float (&LS)[2 * CW],
-                                            unsigned (&cnt)[6], const int32_t* cmap = nullptr) {
+                                            Cnt& cnt, const int32_t* cmap = nullptr) {
     if constexpr (CC < CW) {
         const int s = c * CW + CC;
         if (s < a.r) {
@@ -684,7 +697,7 @@ __device__ __forceinline__ void chunk_steps(const SweepArgs& a, int c, const flo
 // Alg. 2 on one segment (or on this block's part [lo, lo + STRIDE*E) of a long segment).
 // PREFETCH keeps the next tile chunk in flight while the current one is processed; CW is
 // the tile chunk width (coordinates per chunk).
-template <int STRIDE, bool PREFETCH, bool LA, int CW, class Red, class St>
+template <int STRIDE, bool PREFETCH, bool LA, int CW, bool STATS = true, class Red, class St>
 __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool active, int lane,
                                               int lo, bool count_stats, float* xs, Red& red, St& st) {
     constexpr int E = St::kE;
@@ -733,7 +746,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool 
         const float ri = fast_rcp((float)st.ax[e] + a.eps_log);
         st.set_wu(e, st.v(e) * ri, st.v(e) * ri * ri);
     }
-    unsigned cnt[6] = {0, 0, 0, 0, 0, 0};
+    Counters<STATS> cnt;
     load_chunk<E, STRIDE, CW>(a, st, L, lo, lane, 0, cur);
     for (int c = 0; c < nchunks; ++c) {
         float4 nxt[E][kQuads<CW>];
@@ -755,7 +768,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool 
                 }
             }
             red.sum(LS, 0);
-            cnt[1] += 1;
+            cnt.add(1);
         }
         chunk_steps<0, E, LA, CW>(a, c, cur, st, xs, red, LS, cnt);
         if (PREFETCH) {
@@ -775,9 +788,11 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool 
             if (l < L) a.Mout[base + l] = st.ax[e];
         }
     }
-    if (a.stats && count_stats && lane == 0) {
+    if constexpr (STATS) {
+        if (a.stats && count_stats && lane == 0) {
 #pragma unroll
-        for (int q = 0; q < 6; ++q) atomicAdd(&a.stats[q], (unsigned long long)cnt[q]);
+            for (int q = 0; q < 6; ++q) atomicAdd(&a.stats[q], (unsigned long long)cnt.c[q]);
+        }
     }
 }
 
@@ -785,7 +800,7 @@ __device__ __forceinline__ void sweep_segment(const SweepArgs& a, int seg, bool 
 // latency is exposed without prefetching).
 constexpr int kFusedCW = 8;
 
-template <int G, int E, bool LA, int CW = kFusedCW>
+template <int G, int E, bool LA, int CW = kFusedCW, bool STATS = true>
 __device__ __forceinline__ void sweep_block(const SweepArgs& ag, const BlockWork& wk, const int32_t* segs,
                                             float* xs_all, float* red_lds, double* sA_lds) {
     const int slot = threadIdx.x / G;
@@ -804,17 +819,17 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& ag, const BlockWork
     RegElems<E> st;
     if constexpr (G <= 64) {
         WaveReducer<G> red;
-        sweep_segment<G, false, LA, CW>(a, seg, active, lane, 0, true, xs, red, st);
+        sweep_segment<G, false, LA, CW, STATS>(a, seg, active, lane, 0, true, xs, red, st);
     } else {
         BlockReducer<G> red{red_lds, 0, nullptr};
-        sweep_segment<G, false, LA, CW>(a, seg, active, lane, 0, true, xs, red, st);
+        sweep_segment<G, false, LA, CW, STATS>(a, seg, active, lane, 0, true, xs, red, st);
         __syncthreads();
     }
     if (active)
         for (int s = lane; s < a.r; s += G) a.X[(int64_t)seg * a.r + a.ids[s]] = xs[s];
 }
 
-template <int G, int E, int CW>
+template <int G, int E, int CW, bool STATS = true>
 __device__ __forceinline__ void sweep_block_lds(const SweepArgs& ag, const BlockWork& wk, const int32_t* segs,
                                                 float* xs_all, double* sA_lds, int32_t* s_id, float* s_v,
                                                 float* red_lds) {
@@ -834,10 +849,10 @@ __device__ __forceinline__ void sweep_block_lds(const SweepArgs& ag, const Block
     st.vp = s_v + slot * G * E + lane;
     if constexpr (G <= 64) {
         WaveReducer<G> red;
-        sweep_segment<G, false, true, CW>(a, seg, active, lane, 0, true, xs, red, st);
+        sweep_segment<G, false, true, CW, STATS>(a, seg, active, lane, 0, true, xs, red, st);
     } else {
         BlockReducer<G> red{red_lds, 0, nullptr};
-        sweep_segment<G, false, true, CW>(a, seg, active, lane, 0, true, xs, red, st);
+        sweep_segment<G, false, true, CW, STATS>(a, seg, active, lane, 0, true, xs, red, st);
         __syncthreads();
     }
     if (active)
@@ -848,7 +863,7 @@ __device__ __forceinline__ void sweep_block_lds(const SweepArgs& ag, const Block
 // LA256 selects the lookahead form for the 256-lane variant.  The kernel is latency-bound
 // (each coordinate is a dependent chain of sums, a reduction and Newton logic), so it runs
 // at 4 waves per SIMD (at most 128 registers) without a prefetched second tile chunk.
-template <bool LA256>
+template <bool LA256, bool STATS>
 __global__ void __launch_bounds__(kFusedThreads, LA256 ? 2 : 4)
 k_sweep_fused(const SweepArgs* __restrict__ tab, const BlockWork* __restrict__ work,
               const int32_t* __restrict__ segs) {
@@ -860,22 +875,27 @@ k_sweep_fused(const SweepArgs* __restrict__ tab, const BlockWork* __restrict__ w
     const BlockWork wk = work[blockIdx.x];
     const SweepArgs a = tab[wk.prob];
     switch (wk.variant) {
-        case 0: sweep_block<8, 4, false>(a, wk, segs, xs_all, red, sA_lds); break;
-        case 1: sweep_block<16, 4, false>(a, wk, segs, xs_all, red, sA_lds); break;
-        case 2: sweep_block<32, 4, false>(a, wk, segs, xs_all, red, sA_lds); break;
-        case 3: sweep_block<64, 4, false>(a, wk, segs, xs_all, red, sA_lds); break;
-        case 4: sweep_block_lds<64, 8, 4>(a, wk, segs, xs_all, sA_lds, s_id, s_v, red); break;
-        default: sweep_block<256, 4, LA256>(a, wk, segs, xs_all, red, sA_lds); break;
+        case 0: sweep_block<8, 4, false, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
+        case 1: sweep_block<16, 4, false, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
+        case 2: sweep_block<32, 4, false, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
+        case 3: sweep_block<64, 4, false, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
+        case 4: sweep_block_lds<64, 8, 4, STATS>(a, wk, segs, xs_all, sA_lds, s_id, s_v, red); break;
+        default: sweep_block<256, 4, LA256, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
     }
 }
 
 hipError_t launch_sweep_fused(const SweepArgs* tab, const BlockWork* work, const int32_t* segs,
-                              int nblocks, bool lookahead, hipStream_t stream) {
+                              int nblocks, bool lookahead, bool stats, hipStream_t stream) {
     if (nblocks <= 0) return hipSuccess;
-    if (lookahead)
-        hipLaunchKernelGGL(k_sweep_fused<true>, dim3(nblocks), dim3(kFusedThreads), 0, stream, tab, work, segs);
+    const dim3 grid(nblocks), block(kFusedThreads);
+    if (lookahead && stats)
+        hipLaunchKernelGGL((k_sweep_fused<true, true>), grid, block, 0, stream, tab, work, segs);
+    else if (lookahead)
+        hipLaunchKernelGGL((k_sweep_fused<true, false>), grid, block, 0, stream, tab, work, segs);
+    else if (stats)
+        hipLaunchKernelGGL((k_sweep_fused<false, true>), grid, block, 0, stream, tab, work, segs);
     else
-        hipLaunchKernelGGL(k_sweep_fused<false>, dim3(nblocks), dim3(kFusedThreads), 0, stream, tab, work, segs);
+        hipLaunchKernelGGL((k_sweep_fused<false, false>), grid, block, 0, stream, tab, work, segs);
     return hipGetLastError();
 }
 
@@ -1125,7 +1145,7 @@ __device__ __forceinline__ void foldin_segment(const FoldinArgs& f, const SweepA
     if constexpr (G > 64) __syncthreads();
     double kl_prev = doc_kl<G, E>(f, st, lane, xs, red);
     double kl = kl_prev;
-    unsigned cnt[6] = {0, 0, 0, 0, 0, 0};
+    Counters<true> cnt;
     const int nchunks = (f.r + kChunk - 1) / kChunk;
     int p = 0;
     while (p < f.max_passes) {
@@ -1150,7 +1170,7 @@ __device__ __forceinline__ void foldin_segment(const FoldinArgs& f, const SweepA
                     }
                 }
                 red.sum(LS, 0);
-                cnt[1] += 1;
+                cnt.add(1);
             }
             chunk_steps<0, E, LA, kChunk>(a, c, cur, st, xs, red, LS, cnt, perm_lds);
         }
@@ -1167,7 +1187,7 @@ __device__ __forceinline__ void foldin_segment(const FoldinArgs& f, const SweepA
     }
     if (a.stats && lane == 0) {
 #pragma unroll
-        for (int q = 0; q < 6; ++q) atomicAdd(&a.stats[q], (unsigned long long)cnt[q]);
+        for (int q = 0; q < 6; ++q) atomicAdd(&a.stats[q], (unsigned long long)cnt.c[q]);
     }
 }
 

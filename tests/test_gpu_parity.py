@@ -184,15 +184,22 @@ def test_empty_columns_and_rows_go_to_zero():
 
 
 def test_stats_counters():
+    """The binned launch keeps counters only when the handle collects statistics (another
+    kernel instance); both instances must give the same factors bit for bit."""
     prob = CASES["tiny"]()
-    dev = P.upload(prob, "cuda")
-    h = P.nmfkl_create(dev, P.nmfkl_params_default(collect_stats=1))
-    P.nmfkl_sweep_F(h, 0)
-    P.nmfkl_sweep_W(h, 0)
-    st = P.nmfkl_get_stats(h)
-    P.nmfkl_destroy(h)
+    out = {}
+    for collect in (1, 0):
+        dev = P.upload(prob, "cuda")
+        h = P.nmfkl_create(dev, P.nmfkl_params_default(collect_stats=collect))
+        P.nmfkl_sweep_F(h, 0)
+        P.nmfkl_sweep_W(h, 0)
+        if collect:
+            st = P.nmfkl_get_stats(h)
+        out[collect] = (dev.W.cpu().numpy(), dev.F.cpu().numpy())
+        P.nmfkl_destroy(h)
     assert st["coords"] == (prob.m + prob.n) * prob.r
     assert st["evals"] >= st["coords"] and st["steps"] > 0
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
 def long_corpus(seed=0):
