@@ -1320,7 +1320,7 @@ hipError_t batch_enqueue(nmfkl_batch* b, hipStream_t s, int nsweeps, bool cooper
             if ((e = launch_permute_jobs(jobs, np, b->perm_blocks[half], k, b->t_dev, s)) != hipSuccess) return e;
             if ((e = launch_finalize_jobs(jobs, np, b->nsum[half], s)) != hipSuccess) return e;
             if ((e = enqueue_plan(b->plan[half], b->argtab + (size_t)half * np, b->coop_words,
-                                  b->dev_err, cooperative, la, true, s, nullptr, 0, 0)) != hipSuccess)
+                                  b->dev_err, cooperative, la, b->prm.collect_stats != 0, s, nullptr, 0, 0)) != hipSuccess)
                 return e;
         }
     return hipSuccess;
