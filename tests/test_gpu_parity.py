@@ -362,6 +362,25 @@ def test_ablation_step_parity(flags):
     assert relf(Fg, Fo) <= 1e-4
 
 
+def test_guard_rejections_restore_the_state():
+    """With j_max = 0 every decreasing step that fails the descent guard is abandoned at
+    once (Alg. 2 with the guard of §3): the lane state must go back to the model before the
+    step.  Both halves (the W-half has rows for the long-segment kernels), GPU vs oracle;
+    the oracle's counters confirm that rejections happen."""
+    prob = CASES["corpus_mid"]()
+    t = 2
+    ids = oracle.permutation(0, t, 0, prob.r)
+    prm = oracle.params(j_max=0)
+    Fo, _, st_f = oracle.sweep_F(prob, prob.W0.astype(np.float64), prob.F0.astype(np.float64), ids, prm)
+    Wo, _, st_w = oracle.sweep_W(prob, prob.F0.astype(np.float64), prob.W0.astype(np.float64), ids, prm)
+    assert st_f["rejects"] > 0 and st_w["rejects"] > 0
+    Fg = gpu_half(prob, prob.W0, prob.F0, t, "F", P.nmfkl_params_default(j_max=0))
+    Wg = gpu_half(prob, prob.W0, prob.F0, t, "W", P.nmfkl_params_default(j_max=0))
+    print(f"j_max = 0: F rel {relf(Fg, Fo):.2e} flips {flips(Fg, Fo)}, W rel {relf(Wg, Wo):.2e} "
+          f"flips {flips(Wg, Wo)}; oracle rejections F {st_f['rejects']} W {st_w['rejects']}")
+    assert relf(Fg, Fo) <= 1e-4 and relf(Wg, Wo) <= 1e-4
+
+
 def _bf16_round(a):
     """Round float32 values to the nearest bfloat16 (ties to even), kept as float32."""
     u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
