@@ -238,6 +238,7 @@ def serving_leg(P, W, arrivals, ptr, idx, val, window_s, log):
     buf = P.PollBuffer(4096, r)
     lat = np.full(N, np.nan)
     passes = np.zeros(N, np.int32)
+    deferred = np.zeros(N, bool)     # refused at least once because the memory budget was full
     waiting = collections.deque()
     nxt, ndone = 0, 0
     t0 = time.monotonic() + 0.05
@@ -250,6 +251,7 @@ def serving_leg(P, W, arrivals, ptr, idx, val, window_s, log):
         while waiting:
             d = waiting[0]
             if P.nmfkl_server_submit(srv, d, *doc(d)) != 0:
+                deferred[d] = True
                 break
             waiting.popleft()
         k = P.nmfkl_server_poll_into(srv, buf)
@@ -266,7 +268,8 @@ def serving_leg(P, W, arrivals, ptr, idx, val, window_s, log):
     srv_out = {"docs": N, "wall_s": round(served_s, 3), "docs_per_s": N / served_s,
                "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
                "p999_ms": float(np.percentile(lat, 99.9) * 1e3),
-               "passes_median": float(np.median(passes)), "passes_max": int(passes.max())}
+               "passes_median": float(np.median(passes)), "passes_max": int(passes.max()),
+               "rejected": int(N - ndone), "deferred_by_admission": int(deferred.sum())}
     log(f"[bench] serving: server {srv_out}")
 
     # ---- plain: one nmfkl_foldin call per request, in arrival order, for window_s seconds
