@@ -7,9 +7,11 @@
  * GPU path is checked against.  Only the test suite, the smoke check and the benchmark's
  * CPU-baseline leg may load it.  It shares no code, header or table with the GPU library.
  *
- * Everything is double precision, summed sequentially in storage order, with no blocking
- * or fusion.  Columns (F-half) and rows (W-half) are independent subproblems (the
- * separability identity, eq. 3) and are run in parallel with OpenMP, as Alg. 1 states.
+ * Everything is double precision with no blocking or fusion.  Sums over the nonzeros of
+ * one column or row run sequentially in storage order; the objective adds the columns'
+ * sums in column order.  No result depends on the thread count.  Columns (F-half) and
+ * rows (W-half) are independent subproblems (the separability identity, eq. 3) and are
+ * run in parallel with OpenMP, as Alg. 1 states.
  *
  * Notation (the paper's, with its W r x n and F r x m stored transposed, point-major):
  *   V   n x m sparse counts, as CSC (columns = documents) and CSR (rows = words)
@@ -308,18 +310,25 @@ double orc_objective(int32_t n, int32_t m, int32_t r, const int64_t* csc_ptr,
     orc_factor_sums(m, r, F, sf);
     double total = 0.0;
     for (int32_t k = 0; k < r; ++k) total += sw[k] * sf[k];
-    double part = 0.0;
-#pragma omp parallel for schedule(static) reduction(+ : part)
+    /* each column's terms in storage order, then the columns in order: the same value
+     * for any number of threads */
+    double* col = (double*)malloc((size_t)(m > 0 ? m : 1) * sizeof(double));
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < m; ++j) {
+        double cj = 0.0;
         for (int64_t q = csc_ptr[j]; q < csc_ptr[j + 1]; ++q) {
             double v = csc_val[q];
             if (v == 0.0) continue;
             const double* w = W + (int64_t)csc_idx[q] * r;
             double M = 0.0;
             for (int32_t k = 0; k < r; ++k) M += w[k] * F[j * r + k];
-            part += v * log(v / M) - v;
+            cj += v * log(v / M) - v;
         }
+        col[j] = cj;
     }
+    double part = 0.0;
+    for (int64_t j = 0; j < m; ++j) part += col[j];
+    free(col);
     free(sw);
     free(sf);
     return part + total;

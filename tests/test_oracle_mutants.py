@@ -21,7 +21,10 @@ MUTANTS = {
     "Newton sign": ("double xn = x[k] - g / h;", "double xn = x[k] + g / h;"),
     "guard removed": ("if (prm->guard && d < 0.0) {", "if (0) {"),
     "Ax ignores x": ("if (x[k] != 0.0) s += a[k] * x[k];", "if (x[k] != 0.0) s += a[k];"),
-    "objective drops -v": ("part += v * log(v / M) - v;", "part += v * log(v / M);"),
+    "objective drops -v": ("cj += v * log(v / M) - v;", "cj += v * log(v / M);"),
+    "column_kl drops -v": ("kl += v[l] * log(v[l] / M) - v[l];", "kl += v[l] * log(v[l] / M);"),
+    "column_kl drops sumA x": ("for (int32_t k = 0; k < r; ++k) kl += sumA[k] * x[k];",
+                               "for (int32_t k = 0; k < r; ++k) kl += 0.0 * sumA[k] * x[k];"),
     "objective drops model mass": ("total += sw[k] * sf[k];", "total += sw[k];"),
     "sums wrong column": ("sumA[k] += A[p * r + k];", "sumA[k] += A[p * r];"),
     "philox drops key": ("uint64_t n0 = hi1 ^ c1 ^ k0,", "uint64_t n0 = hi1 ^ c1,"),
@@ -45,6 +48,7 @@ PIN_TESTS = [
     ("test_inner_loop_production_tolerances_never_increase", {}),
     ("test_guard_rejects_overshooting_decrease", {}),
     ("test_objective_matches_dense_library_kl", {}),
+    ("test_column_kl_matches_library_kl", {}),
     ("test_factor_sums_match_numpy", {}),
     ("test_half_sweeps_never_increase_objective", {}),
     ("test_r1_closed_form_independence_model", {}),

@@ -262,6 +262,39 @@ def test_objective_explicit_zero_and_zero_model(orc):
     assert np.isinf(orc.objective(prob, W2, F))
 
 
+def test_column_kl_matches_library_kl(orc):
+    """eq. 1 restricted to one column with the fixed factor A (the fold-in stop rule):
+    scipy's generalised KL over every point of the dense column against the model A x.
+    Its sum over the points without a count is the model mass sum_k sumA_k x_k, so the
+    library value pins the log terms, the -v terms and the mass term together."""
+    rng = np.random.default_rng(21)
+    for trial in range(40):
+        A, idx, v, x = random_column(rng, n=20, r=5)
+        x = x + 0.05                       # strictly positive model at every point
+        if trial % 4 == 0:
+            v[rng.random(v.size) < 0.3] = 0.0      # explicit zeros of the column
+        sumA = A.sum(axis=0)
+        vd = np.zeros(A.shape[0])
+        vd[idx] = v
+        ref = kl_div(vd, A @ x).sum()
+        assert orc.column_kl(idx, v, A, sumA, x) == pytest.approx(ref, rel=1e-12, abs=1e-12)
+
+
+def test_objective_independent_of_thread_count(orc):
+    """The objective's summation order is fixed: one thread and all threads agree bit for bit."""
+    prob = workloads.config(0, seed=2)
+    rng = np.random.default_rng(2)
+    W = rng.random((prob.n, prob.r))
+    F = rng.random((prob.m, prob.r))
+    threads = orc.threads()
+    try:
+        orc.set_threads(1)
+        d1 = orc.objective(prob, W, F)
+    finally:
+        orc.set_threads(threads)
+    assert orc.objective(prob, W, F) == d1
+
+
 def test_factor_sums_match_numpy(orc):
     rng = np.random.default_rng(6)
     A = rng.random((1000, 7))
