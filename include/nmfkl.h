@@ -317,6 +317,21 @@ int nmfkl_model_create(const float* W, int32_t n, int32_t r, const nmfkl_params*
 int nmfkl_foldin(nmfkl_model* m, int32_t ndocs, const int64_t* doc_ptr, const int32_t* word_idx,
                  const float* counts, float* F_out, int32_t* passes_out, double* kl_out);
 
+/* nmfkl_foldin for callers that cannot allocate memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same arguments, kernels and results
+ * as nmfkl_foldin, but the call allocates nothing on the device or the host heap.  Its
+ * scratch (the validation flags and the documents grouped by kernel variant, 64 KiB) is one
+ * static device array per GPU, held until the process ends; the document pointers are
+ * checked and grouped on the device.  Limit: at most 16384 documents per call
+ * (NMFKL_E_UNSUPPORTED beyond); other errors as nmfkl_foldin (NMFKL_E_INVAL for malformed
+ * documents, NMFKL_E_UNSUPPORTED for a document above 5120 distinct words).  The model's
+ * stream must belong to the current device.  Synchronises the model's stream (twice: to
+ * read the checks, and before returning).  Every call on one GPU shares that GPU's
+ * scratch: calls that overlap on one GPU (from several host threads) race and must be
+ * serialised by the caller. */
+int nmfkl_foldin_noalloc(nmfkl_model* m, int32_t ndocs, const int64_t* doc_ptr, const int32_t* word_idx,
+                         const float* counts, float* F_out, int32_t* passes_out, double* kl_out);
+
 /* Counters of the fold-in kernels (params.collect_stats).  Synchronises. */
 int nmfkl_model_get_stats(nmfkl_model* m, nmfkl_stats* out);
 const char* nmfkl_model_last_error(const nmfkl_model* m);

@@ -31,7 +31,7 @@ EXPORTED_SYMBOLS = [
     "nmfkl_objective", "nmfkl_objective_carried", "nmfkl_objective_enqueue", "nmfkl_objective_read",
     "nmfkl_invalidate_model", "nmfkl_get_stats", "nmfkl_get_timings",
     "nmfkl_reset_timings", "nmfkl_destroy", "nmfkl_last_error",
-    "nmfkl_model_create", "nmfkl_foldin", "nmfkl_model_get_stats", "nmfkl_model_last_error",
+    "nmfkl_model_create", "nmfkl_foldin", "nmfkl_foldin_noalloc", "nmfkl_model_get_stats", "nmfkl_model_last_error",
     "nmfkl_model_destroy", "nmfkl_server_create", "nmfkl_server_submit", "nmfkl_server_poll",
     "nmfkl_server_pending", "nmfkl_server_last_error", "nmfkl_server_destroy",
     "nmfkl_batch_create", "nmfkl_batch_run", "nmfkl_batch_objective", "nmfkl_batch_tune",
@@ -149,6 +149,7 @@ def load(path: str | None = None):
     lib.nmfkl_last_error.restype = ctypes.c_char_p
     lib.nmfkl_model_create.argtypes = [vp, i32, i32, ctypes.POINTER(NmfklParams), vp, ctypes.POINTER(vp)]
     lib.nmfkl_foldin.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+    lib.nmfkl_foldin_noalloc.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
     lib.nmfkl_model_get_stats.argtypes = [vp, ctypes.POINTER(NmfklStats)]
     lib.nmfkl_model_destroy.argtypes = [vp]
     lib.nmfkl_server_create.argtypes = [vp, i64, i32, i32, ctypes.POINTER(vp)]
@@ -394,6 +395,22 @@ def nmfkl_foldin(m: Model, doc_ptr, word_idx, counts):
     kl = torch.empty(nd, dtype=torch.float64, device=dev)
     _mcheck(load().nmfkl_foldin(m._ptr, nd, doc_ptr.data_ptr(), word_idx.data_ptr(), counts.data_ptr(),
                                 F.data_ptr(), passes.data_ptr(), kl.data_ptr()), m._ptr)
+    return F, passes, kl
+
+
+def nmfkl_foldin_noalloc(m: Model, doc_ptr, word_idx, counts, F, passes, kl):
+    """nmfkl_foldin into caller-provided device outputs (F ndocs x r float32, passes int32,
+    kl float64); the library allocates nothing (at most 16384 documents per call)."""
+    import torch
+    nd = doc_ptr.numel() - 1
+    for t, dt, shape in ((F, torch.float32, (nd, m.r)), (passes, torch.int32, (nd,)), (kl, torch.float64, (nd,))):
+        if t.dtype != dt or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shape:
+            raise ValueError(f"output must be a contiguous {dt} device tensor of shape {shape}")
+    for t, dt in ((doc_ptr, torch.int64), (word_idx, torch.int32), (counts, torch.float32)):
+        if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"documents must be contiguous device tensors ({dt})")
+    _mcheck(load().nmfkl_foldin_noalloc(m._ptr, nd, doc_ptr.data_ptr(), word_idx.data_ptr(), counts.data_ptr(),
+                                        F.data_ptr(), passes.data_ptr(), kl.data_ptr()), m._ptr)
     return F, passes, kl
 
 

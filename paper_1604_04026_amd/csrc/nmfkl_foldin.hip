@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -548,3 +549,206 @@ int nmfkl_server_destroy(nmfkl_server* s) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------- fold-in without allocation
+// nmfkl_foldin_noalloc: the scratch of nmfkl_foldin (validation flags and the documents
+// grouped by kernel variant) lives in one file-scope device array instead of hipMalloc'd
+// buffers, and the document pointers are checked and grouped on the device, so the call
+// allocates nothing on the device or the host heap.  Each device holds its own copy of the
+// array; the host takes its address once per device with hipGetSymbolAddress and passes
+// that address to the kernels (the array's name is not a device address in host code).
+namespace {
+
+constexpr int kNoAllocMaxDocs = 16384;
+constexpr int kNoAllocDocsOffset = 256;   // bytes: the header, then the grouped document list
+constexpr size_t kNoAllocBytes = kNoAllocDocsOffset + sizeof(int32_t) * (size_t)kNoAllocMaxDocs;
+constexpr int kMaxDevices = 64;
+
+// Flag bits of the header beyond the shared validation bits.
+constexpr unsigned kTooLong = 1u << 8;      // a document above the largest fold-in variant
+constexpr unsigned kTooManyWords = 1u << 9; // more than 2^31 - 1 words
+constexpr unsigned kNullWords = 1u << 10;   // words present but a null index or count array
+
+struct NoAllocHeader {
+    unsigned flags;                  // validation bits (kBad*, kTooLong, ...)
+    int32_t count[kFoldinVariants];  // documents per variant
+    int64_t nnz;                     // doc_ptr[ndocs] (valid when kBadPtr is clear)
+};
+static_assert(sizeof(NoAllocHeader) <= kNoAllocDocsOffset, "header must fit before the list");
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+std::mutex g_scratch_mutex;
+unsigned char* g_scratch_addr[kMaxDevices] = {};
+
+// The device address of `scratch` on device dev (current), looked up once per device.
+hipError_t scratch_address(int dev, unsigned char** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[dev] = static_cast<unsigned char*>(p);
+    }
+    *out = g_scratch_addr[dev];
+    return hipSuccess;
+}
+
+__device__ __forceinline__ int foldin_variant(int64_t L) {
+    for (int v = 0; v < kFoldinVariants; ++v)
+        if (L <= kFoldinCapacity[v]) return v;
+    return -1;
+}
+
+// One block: checks the document pointers (doc_ptr[0] = 0, monotone, lengths within the
+// largest variant, total below 2^31), counts the documents per variant and writes their
+// indices grouped by variant, in document order inside each group, after the header.  Every
+// header field is written here, so nothing in the scratch needs clearing first.
+constexpr int kGroupThreads = 1024;
+__global__ void __launch_bounds__(kGroupThreads)
+k_group_docs_noalloc(const int64_t* __restrict__ ptr, int ndocs, const int32_t* idx, const float* val,
+                     unsigned char* base) {
+    __shared__ unsigned s_flags;
+    __shared__ int s_count[kFoldinVariants];
+    __shared__ int s_wave[kGroupThreads / 64][kFoldinVariants];
+    __shared__ int s_run[kFoldinVariants];
+    NoAllocHeader* hdr = reinterpret_cast<NoAllocHeader*>(base);
+    int32_t* list = reinterpret_cast<int32_t*>(base + kNoAllocDocsOffset);
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    if (tid == 0) s_flags = 0u;
+    if (tid < kFoldinVariants) { s_count[tid] = 0; s_run[tid] = 0; }
+    __syncthreads();
+    unsigned bad = 0u;
+    int cnt[kFoldinVariants] = {0, 0, 0, 0, 0};
+    for (int d = tid; d < ndocs; d += kGroupThreads) {
+        const int64_t p0 = ptr[d], p1 = ptr[d + 1];
+        if (d == 0 && p0 != 0) bad |= kBadPtr;
+        if (p1 < p0) { bad |= kBadPtr; continue; }
+        const int v = foldin_variant(p1 - p0);
+        if (v < 0) bad |= kTooLong;
+        else cnt[v] += 1;
+    }
+    if (bad) atomicOr(&s_flags, bad);
+#pragma unroll
+    for (int v = 0; v < kFoldinVariants; ++v)
+        if (cnt[v]) atomicAdd(&s_count[v], cnt[v]);
+    __syncthreads();
+    int off[kFoldinVariants];
+    int acc = 0;
+#pragma unroll
+    for (int v = 0; v < kFoldinVariants; ++v) { off[v] = acc; acc += s_count[v]; }
+    // stable grouping, one chunk of kGroupThreads documents at a time
+    for (int c0 = 0; c0 < ndocs; c0 += kGroupThreads) {
+        const int d = c0 + tid;
+        int v = -1;
+        if (d < ndocs) {
+            const int64_t p0 = ptr[d], p1 = ptr[d + 1];
+            if (p1 >= p0) v = foldin_variant(p1 - p0);
+        }
+        int before[kFoldinVariants];
+#pragma unroll
+        for (int k = 0; k < kFoldinVariants; ++k) {
+            const unsigned long long mask = __ballot(v == k);
+            before[k] = __popcll(mask & ((1ull << lane) - 1ull));
+            if (lane == 0) s_wave[wave][k] = __popcll(mask);
+        }
+        __syncthreads();
+        if (v >= 0) {
+            int pos = off[v] + s_run[v] + before[v];
+            for (int q = 0; q < wave; ++q) pos += s_wave[q][v];
+            list[pos] = d;
+        }
+        __syncthreads();
+        if (tid < kFoldinVariants) {
+            int t = 0;
+            for (int q = 0; q < kGroupThreads / 64; ++q) t += s_wave[q][tid];
+            s_run[tid] += t;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        unsigned f = s_flags;
+        int64_t nnz = 0;
+        if (!(f & kBadPtr)) {
+            nnz = ndocs > 0 ? ptr[ndocs] : 0;
+            if (nnz > (int64_t)INT32_MAX) f |= kTooManyWords;
+            if (nnz > 0 && (!idx || !val)) f |= kNullWords;
+        }
+        hdr->flags = f;
+        for (int v = 0; v < kFoldinVariants; ++v) hdr->count[v] = s_count[v];
+        hdr->nnz = nnz;
+    }
+}
+
+// Word ids in [0, n) and strictly increasing per document, counts finite and >= 0: block b
+// checks documents b, b + gridDim.x, ...  Runs only over pointers the grouping accepted.
+__global__ void __launch_bounds__(256)
+k_validate_docs_noalloc(const int64_t* __restrict__ ptr, const int32_t* __restrict__ idx,
+                        const float* __restrict__ val, int ndocs, int n, unsigned char* base) {
+    NoAllocHeader* hdr = reinterpret_cast<NoAllocHeader*>(base);
+    if (hdr->flags & (kBadPtr | kTooManyWords | kNullWords)) return;
+    unsigned bad = 0u;
+    for (int d = blockIdx.x; d < ndocs; d += gridDim.x) {
+        const int64_t p0 = ptr[d], p1 = ptr[d + 1];
+        for (int64_t q = p0 + threadIdx.x; q < p1; q += blockDim.x) {
+            const int32_t i = idx[q];
+            if (i < 0 || i >= n) bad |= kBadIndex;
+            if (q > p0 && idx[q - 1] >= i) bad |= kBadOrder;
+            const float v = val[q];
+            if (!(v >= 0.0f) || !isfinite(v)) bad |= kBadValue;
+        }
+    }
+    if (bad) atomicOr(&hdr->flags, bad);
+}
+
+}  // namespace
+
+extern "C" int nmfkl_foldin_noalloc(nmfkl_model* m, int32_t ndocs, const int64_t* doc_ptr, const int32_t* word_idx,
+                                    const float* counts, float* F_out, int32_t* passes_out, double* kl_out) {
+    if (!m) return mfail(nullptr, NMFKL_E_INVAL, "null model");
+    if (ndocs < 0) return mfail(m, NMFKL_E_INVAL, "ndocs must be >= 0");
+    if (ndocs > kNoAllocMaxDocs)
+        return mfail(m, NMFKL_E_UNSUPPORTED, "nmfkl_foldin_noalloc takes at most 16384 documents per call");
+    if (ndocs == 0) return NMFKL_OK;
+    if (!doc_ptr || !F_out || !passes_out || !kl_out) return mfail(m, NMFKL_E_INVAL, "null pointer");
+    int dev = -1;
+    MHIP(m, hipGetDevice(&dev));
+    if (m->stream) {
+        int sdev = -1;
+        MHIP(m, hipStreamGetDevice(m->stream, &sdev));
+        if (sdev != dev) return mfail(m, NMFKL_E_INVAL, "the model's stream belongs to another device than the current one");
+    }
+    if (dev < 0 || dev >= kMaxDevices) return mfail(m, NMFKL_E_UNSUPPORTED, "device ordinal beyond 63");
+    unsigned char* base = nullptr;
+    MHIP(m, scratch_address(dev, &base));
+    hipLaunchKernelGGL(k_group_docs_noalloc, dim3(1), dim3(kGroupThreads), 0, m->stream, doc_ptr, ndocs, word_idx,
+                       counts, base);
+    MHIP(m, hipGetLastError());
+    const int vblocks = std::min(ndocs, 2048);
+    hipLaunchKernelGGL(k_validate_docs_noalloc, dim3(vblocks), dim3(256), 0, m->stream, doc_ptr, word_idx, counts,
+                       ndocs, m->n, base);
+    MHIP(m, hipGetLastError());
+    NoAllocHeader hdr;
+    MHIP(m, hipMemcpyAsync(&hdr, base, sizeof(hdr), hipMemcpyDeviceToHost, m->stream));
+    MHIP(m, hipStreamSynchronize(m->stream));
+    if (hdr.flags & kBadPtr) return mfail(m, NMFKL_E_INVAL, "doc_ptr[0] must be 0 and doc_ptr monotone");
+    if (hdr.flags & kNullWords) return mfail(m, NMFKL_E_INVAL, "null word/count pointer");
+    if (hdr.flags & kTooManyWords) return mfail(m, NMFKL_E_UNSUPPORTED, "more than 2^31-1 words in one call");
+    if (hdr.flags & kTooLong)
+        return mfail(m, NMFKL_E_UNSUPPORTED, "a document has more distinct words than fold-in supports (5120)");
+    if (hdr.flags)
+        return mfail(m, NMFKL_E_INVAL, "invalid documents: word id out of range, ids not increasing, or count negative / not finite");
+    int off[kFoldinVariants], cnt[kFoldinVariants], pos = 0;
+    for (int v = 0; v < kFoldinVariants; ++v) {
+        off[v] = pos;
+        cnt[v] = hdr.count[v];
+        pos += cnt[v];
+    }
+    const int32_t* list = reinterpret_cast<const int32_t*>(base + kNoAllocDocsOffset);
+    const FoldinArgs f = foldin_args(m, doc_ptr, word_idx, counts, F_out, passes_out, kl_out);
+    const int rc = launch_grouped(m, f, list, off, cnt, m->stream);
+    if (rc) return rc;
+    // the grouped list is read by the kernels: the next call may rewrite it only after they end
+    MHIP(m, hipStreamSynchronize(m->stream));
+    return NMFKL_OK;
+}
