@@ -72,8 +72,9 @@ typedef struct nmfkl_params {
                                   from one half-sweep to the next and recomputed only for the first
                                   half-sweep or after nmfkl_invalidate_model; 1: recomputed from W and
                                   F at the start of every nmfkl_sweep_F (unless nmfkl_objective just
-                                  did).  Identical in exact arithmetic; the carried values differ from
-                                  fresh products only by the float32 rounding of factor updates */
+                                  did).  Identical in exact arithmetic; the carried values move by the
+                                  increments the stored float32 factors actually took, so they differ
+                                  from fresh products only by float64 rounding */
     int32_t collect_stats;     /* 1: count derivative evaluations / steps / guard events (slower) */
     int32_t collect_timings;   /* 1: bracket every launch group with HIP events (nmfkl_get_timings) */
     int32_t tuning;            /* implementation choices that do not change results; bit 0: batched

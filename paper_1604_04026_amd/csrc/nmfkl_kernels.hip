@@ -569,7 +569,12 @@ __device__ __forceinline__ void newton_coordinate(const SweepArgs& a, int s, con
         for (;;) {
 #pragma unroll
             for (int i = 0; i < NACC; ++i) acc[i] = 0.0f;
-            const double dd = (double)d;
+            // the trial coordinate as it will be stored (float32), and the model moved by the
+            // stored increment (exact in float64), so that the model values stay those of the
+            // factors as stored: carried from one half-sweep to the next, they then equal
+            // recomputed ones up to float64 rounding
+            const float xt = xk + d;
+            const double dd = (double)xt - (double)xk;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const double m = fmax(fma(dd, (double)tk[e], axo[e]), 0.0);
@@ -584,7 +589,6 @@ __device__ __forceinline__ void newton_coordinate(const SweepArgs& a, int s, con
             }
             red.sum(acc, OFF);
             cnt.add(1);
-            const float xt = xk + d;
             Pn = sA + (double)a.alpha * xt + (double)a.beta;
             gn = Pn - (double)acc[OFF];
             hn = acc[OFF + 1] + a.alpha;

@@ -237,72 +237,40 @@ def test_long_segments_step_and_trajectory():
     assert np.all(relD <= 1e-5) and relf(Wg, Wo) <= 1e-4 and relf(Fg, Fo) <= 1e-4
 
 
-@pytest.fixture(scope="module")
-def corpus_full():
-    return workloads.config(1, seed=0)
-
-
-def test_sampled_parity_full_size_corpus(corpus_full):
-    """The 50,000 x 100,000, r = 50 corpus in the launch configuration the benchmark times:
-    one F-half and one W-half on the GPU from (W0, F0); the oracle recomputes sampled
-    columns and rows one by one (the 20 heaviest rows included) from the same state."""
-    prob = corpus_full
-    t = 0
-    ids = oracle.permutation(0, t, 0, prob.r)
-    dev = P.upload(prob, "cuda")
-    h = P.nmfkl_create(dev)
-    P.nmfkl_sweep_F(h, t)
-    Fg = dev.F.cpu().numpy()
-    P.nmfkl_sweep_W(h, t)
-    Wg = dev.W.cpu().numpy()
-    P.nmfkl_destroy(h)
-    W0, F0 = prob.W0.astype(np.float64), prob.F0.astype(np.float64)
-    rng = np.random.default_rng(11)
-    sumW = oracle.factor_sums(W0)
-    cols = rng.choice(prob.m, 3000, replace=False)
-    Fo = np.array([oracle.alg2(prob.csc_idx[prob.csc_ptr[j]:prob.csc_ptr[j + 1]],
-                               prob.csc_val[prob.csc_ptr[j]:prob.csc_ptr[j + 1]], W0, sumW, F0[j], ids)[0]
-                   for j in cols])
-    eF = relf(Fg[cols], Fo)
-    # W-half rows from the GPU's F (the state the GPU W-half started from)
-    F1 = Fg.astype(np.float64)
-    sumF = oracle.factor_sums(F1)
-    R = np.diff(prob.csr_ptr)
-    heavy = np.sort(np.argsort(R)[-20:])
-    rows = np.unique(np.concatenate([heavy, rng.choice(prob.n, 1000, replace=False)]))
-    Wo = np.array([oracle.alg2(prob.csr_idx[prob.csr_ptr[i]:prob.csr_ptr[i + 1]],
-                               prob.csr_val[prob.csr_ptr[i]:prob.csr_ptr[i + 1]], F1, sumF, W0[i], ids)[0]
-                   for i in rows])
-    eW = relf(Wg[rows], Wo)
-    eH = relf(Wg[heavy], Wo[np.isin(rows, heavy)])
-    print(f"full corpus sampled: F rel {eF:.2e} (3000 cols), W rel {eW:.2e} ({rows.size} rows), "
-          f"20 heaviest rows rel {eH:.2e}; flips F {flips(Fg[cols], Fo)} W {flips(Wg[rows], Wo)}")
-    assert eF <= 1e-4 and eW <= 1e-4 and eH <= 1e-4
-
-
 def test_carried_objective_and_refresh_mode():
-    """The objective from the carried model values matches the exact one, and the
-    refresh-every-sweep mode follows the same trajectory."""
+    """The two model paths against the oracle over 12 unregularised sweeps (Alg. 1/Alg. 2),
+    with nmfkl_objective_carried inside the loop and the exact objective once at the end.
+    refresh_model = 0 (the default, the path the bench times): each F-half reads the float64
+    model values the previous W-half carried.  refresh_model = 1: they are recomputed from W
+    and F before every F-half (the model-pass timings show it).  Both stay within the
+    tolerances of the oracle, and within 1e-6 of each other (the carried values track the
+    factors as stored)."""
     prob = CASES["corpus_mid"]()
-    sweeps = 6
+    sweeps = 12
     res = {}
     for refresh in (0, 1):
         dev = P.upload(prob, "cuda")
-        h = P.nmfkl_create(dev, P.nmfkl_params_default(refresh_model=refresh))
-        Dc, De = [], []
+        h = P.nmfkl_create(dev, P.nmfkl_params_default(refresh_model=refresh, collect_timings=1))
+        Dc = []
         for t in range(sweeps):
             P.nmfkl_sweep_F(h, t)
             P.nmfkl_sweep_W(h, t)
             Dc.append(P.nmfkl_objective_carried(h))
-            De.append(P.nmfkl_objective(h))
-        res[refresh] = (np.array(Dc), np.array(De), dev.W.cpu().numpy(), dev.F.cpu().numpy())
+        De = P.nmfkl_objective(h)
+        passes = P.nmfkl_get_timings(h)["model"]["launches"]
+        res[refresh] = (np.array(Dc), De, dev.W.cpu().numpy(), dev.F.cpu().numpy(), passes)
         P.nmfkl_destroy(h)
-    for refresh, (Dc, De, W, F) in res.items():
-        assert np.all(np.abs(Dc - De) / De <= 1e-6), (refresh, Dc, De)
     Wo, Fo, Do = oracle.run(prob, sweeps)
-    for refresh, (Dc, De, W, F) in res.items():
-        assert np.all(np.abs(De - Do) / Do <= 1e-5)
+    for refresh, (Dc, De, W, F, passes) in res.items():
+        rel = np.abs(Dc - Do) / Do
+        print(f"refresh_model={refresh}: model passes {passes}; D rel max {rel.max():.2e}, exact vs carried "
+              f"at the end {abs(De - Dc[-1]) / De:.2e}; W {relf(W, Wo):.2e} F {relf(F, Fo):.2e}")
+        assert np.all(rel <= 1e-5)
+        assert abs(De - Dc[-1]) / De <= 1e-6
         assert relf(W, Wo) <= 1e-4 and relf(F, Fo) <= 1e-4
+    # carried: the first F-half and the final exact objective; refreshed: also every later F-half
+    assert res[0][4] == 2 and res[1][4] == sweeps + 1
+    assert relf(res[0][2], res[1][2].astype(np.float64)) <= 1e-6
 
 
 def test_objective_enqueue_then_read_equals_carried():
