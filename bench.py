@@ -86,15 +86,15 @@ def valu_busy_for(group: str):
     return t.get("groups", {}).get(group)
 
 
-def cpu_baseline(prob, seconds: float, keep: int = 0):
-    """The oracle's sweeps for about `seconds`; also returns its objectives and its factors
-    after `keep` sweeps (for the GPU check)."""
+def cpu_baseline(prob, seconds: float, keep=(), min_sweeps: int = 0):
+    """The oracle's sweeps for about `seconds` (and at least `min_sweeps`); also returns its
+    objectives and its factors after each sweep count in `keep` (for the GPU check)."""
     import numpy as np
     import oracle
     W = prob.W0.astype(np.float64)
     F = prob.F0.astype(np.float64)
     D = []
-    kept = None
+    kept = {}
     t0 = time.perf_counter()
     sweeps = 0
     while True:
@@ -103,9 +103,9 @@ def cpu_baseline(prob, seconds: float, keep: int = 0):
         W, _, _ = oracle.sweep_W(prob, F, W, ids)
         D.append(oracle.objective(prob, W, F))
         sweeps += 1
-        if sweeps == keep:
-            kept = (W.copy(), F.copy())
-        if time.perf_counter() - t0 >= seconds or sweeps >= 60:
+        if sweeps in keep:
+            kept[sweeps] = (W.copy(), F.copy())
+        if (time.perf_counter() - t0 >= seconds and sweeps >= min_sweeps) or sweeps >= 60:
             break
     dt = time.perf_counter() - t0
     # the same oracle on one core: the F-half of the first sweep
@@ -154,10 +154,11 @@ def sweep_leg(P, prob, args, log):
     elapsed = time.perf_counter() - t_start
     sweep_ms = [evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)]
     tim = P.nmfkl_get_timings(h)
+    final = (D, P.nmfkl_objective(h), dev.W.cpu().numpy(), dev.F.cpu().numpy())
     P.nmfkl_destroy(h)
     del dev
     log(f"[bench] timed {args.steps} sweeps in {elapsed * 1e3:.2f} ms, final D = {D}")
-    return elapsed, tim, D_warm, sweep_ms, warm_factors
+    return elapsed, tim, D_warm, sweep_ms, warm_factors, final
 
 
 def batched_leg(P, probs, log):
@@ -240,19 +241,22 @@ def serving_leg(P, W, arrivals, ptr, idx, val, window_s, log):
     passes = np.zeros(N, np.int32)
     deferred = np.zeros(N, bool)     # refused at least once because the memory budget was full
     waiting = collections.deque()
-    nxt, ndone = 0, 0
+    nxt, ndone, rejected = 0, 0, 0
     t0 = time.monotonic() + 0.05
     deadline = t0 + arrivals[-1] + 120.0
-    while ndone < N:
+    while ndone + rejected < N:
         now = time.monotonic()
         while nxt < N and t0 + arrivals[nxt] <= now:
             waiting.append(nxt)
             nxt += 1
         while waiting:
             d = waiting[0]
-            if P.nmfkl_server_submit(srv, d, *doc(d)) != 0:
-                deferred[d] = True
-                break
+            try:
+                if P.nmfkl_server_submit(srv, d, *doc(d)) != 0:
+                    deferred[d] = True
+                    break
+            except P.NmfklError:
+                rejected += 1        # refused for good (malformed or beyond the fold-in limits)
             waiting.popleft()
         k = P.nmfkl_server_poll_into(srv, buf)
         for q in range(k):
@@ -265,11 +269,11 @@ def serving_leg(P, W, arrivals, ptr, idx, val, window_s, log):
     t_end = time.monotonic()
     P.nmfkl_server_destroy(srv)
     served_s = t_end - t0
-    srv_out = {"docs": N, "wall_s": round(served_s, 3), "docs_per_s": N / served_s,
-               "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-               "p999_ms": float(np.percentile(lat, 99.9) * 1e3),
+    srv_out = {"docs": N, "wall_s": round(served_s, 3), "docs_per_s": ndone / served_s,
+               "p50_ms": float(np.nanpercentile(lat, 50) * 1e3), "p99_ms": float(np.nanpercentile(lat, 99) * 1e3),
+               "p999_ms": float(np.nanpercentile(lat, 99.9) * 1e3),
                "passes_median": float(np.median(passes)), "passes_max": int(passes.max()),
-               "rejected": int(N - ndone), "deferred_by_admission": int(deferred.sum())}
+               "rejected": int(rejected), "deferred_by_admission": int(deferred.sum())}
     log(f"[bench] serving: server {srv_out}")
 
     # ---- plain: one nmfkl_foldin call per request, in arrival order, for window_s seconds
@@ -391,21 +395,25 @@ def traffic_summarize(fetch_dir, write_dir, out_path):
     print(json.dumps(out, indent=1))
 
 
-def large_run(args, log):
-    """The large corpus (100,000 x 2,000,000, r = 100, ~300M nonzeros): sweeps with float32
-    tiles and with bfloat16-stored tiles from the same initial factors (objective and rate of
-    each, and their difference), and the first sweep's float32 F-half and W-half checked on
-    sampled columns and rows (the heaviest rows included) against the oracle."""
-    import numpy as np
+def large_problem(args, log):
     from paper_1604_04026_amd import workloads
     t0 = time.perf_counter()
     prob = workloads.config(2, seed=args.seed, workers=args.workers,
-                            progress=lambda msg: print(f"[large] {msg} ({time.perf_counter() - t0:.0f} s)",
-                                                       file=sys.stderr, flush=True))
+                            progress=lambda msg: log(f"[large] {msg} ({time.perf_counter() - t0:.0f} s)"))
     log(f"[large] generated n={prob.n} m={prob.m} r={prob.r} nnz={prob.nnz} ({time.perf_counter() - t0:.1f} s)")
+    return prob
+
+
+def large_leg(P, prob, args, log, sweeps: int = 10):
+    """The large corpus (100,000 x 2,000,000, r = 100, ~300M nonzeros): `sweeps` outer
+    iterations with float32 tiles and with bfloat16-stored tiles from the same initial factors
+    (time per iteration, gather-model fraction of HBM peak per launch group and per iteration,
+    the exact objective of each and their difference), and the first iteration's float32
+    F-half and W-half checked on sampled columns and rows (the 20 heaviest rows included)
+    against the oracle."""
+    import numpy as np
     import torch
-    import paper_1604_04026_amd as P
-    torch.cuda.set_device(0)
+    from concurrent.futures import ThreadPoolExecutor
     res = {}
     first = None
     for bf in (0, 1):
@@ -417,14 +425,13 @@ def large_run(args, log):
         P.nmfkl_sweep_W(h, 0)
         if bf == 0:
             first = (Fg, dev.W.cpu().numpy())
-        D1 = P.nmfkl_objective_carried(h)
+        D1 = P.nmfkl_objective(h)
         P.nmfkl_reset_timings(h)
         torch.cuda.synchronize()
         ts = time.perf_counter()
-        for t in range(1, 1 + args.steps):
+        for t in range(1, sweeps):
             P.nmfkl_sweep_F(h, t)
             P.nmfkl_sweep_W(h, t)
-            P.nmfkl_objective_carried(h)
         torch.cuda.synchronize()
         el = time.perf_counter() - ts
         tim = P.nmfkl_get_timings(h)
@@ -432,39 +439,62 @@ def large_run(args, log):
         P.nmfkl_destroy(h)
         del dev
         torch.cuda.empty_cache()
-        res[bf] = {"ms_per_sweep": el * 1e3 / args.steps, "updates_per_s": 2.0 * prob.nnz * prob.r * args.steps / el,
-                   "objective_after_first_sweep": D1, "objective": D, "sweeps": 1 + args.steps,
-                   "groups_ms": {k: round(v["ms_total"] / v["launches"], 4) for k, v in tim.items() if v["launches"]}}
+        ms = el * 1e3 / (sweeps - 1)
+        groups = {k: {"ms": round(v["ms_total"] / v["launches"], 4),
+                      "frac": round(v["gather_bytes"] / (v["ms_total"] / v["launches"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                  for k, v in tim.items() if v["launches"]}
+        step_bytes = sum(v["gather_bytes"] * v["launches"] for v in tim.values()) / (sweeps - 1)
+        res[bf] = {"ms_per_sweep": round(ms, 3), "updates_per_s": 2.0 * prob.nnz * prob.r / (ms * 1e-3),
+                   "step_frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                   "objective_after_first_sweep": D1, "objective": D, "sweeps": sweeps, "groups": groups}
         log(f"[large] tile_bf16={bf}: {res[bf]}")
-    # sampled parity of the first sweep (float32 tiles) against the oracle
+    # sampled parity of the first sweep (float32 tiles) against the oracle, columns and rows in
+    # parallel threads (each oracle call releases the GIL)
     import oracle
     Fg, Wg = first
     ids = oracle.permutation(args.seed, 0, 0, prob.r)
     W0, F0 = prob.W0.astype(np.float64), prob.F0.astype(np.float64)
     rng = np.random.default_rng(7)
     sumW = oracle.factor_sums(W0)
-    cols = rng.choice(prob.m, 500, replace=False)
-    Fo = np.array([oracle.alg2(prob.csc_idx[prob.csc_ptr[j]:prob.csc_ptr[j + 1]],
-                               prob.csc_val[prob.csc_ptr[j]:prob.csc_ptr[j + 1]], W0, sumW, F0[j], ids)[0]
-                   for j in cols])
+    cols = np.sort(rng.choice(prob.m, 500, replace=False))
     F1 = Fg.astype(np.float64)
     sumF = oracle.factor_sums(F1)
     R = np.diff(prob.csr_ptr)
-    heavy = np.sort(np.argsort(R)[-6:])
+    heavy = np.sort(np.argsort(R)[-20:])
     rows = np.unique(np.concatenate([heavy, rng.choice(prob.n, 100, replace=False)]))
-    Wo = np.array([oracle.alg2(prob.csr_idx[prob.csr_ptr[i]:prob.csr_ptr[i + 1]],
-                               prob.csr_val[prob.csr_ptr[i]:prob.csr_ptr[i + 1]], F1, sumF, W0[i], ids)[0]
-                   for i in rows])
-    rel = lambda a, b: float(np.linalg.norm(a.astype(np.float64) - b) / np.linalg.norm(b))
-    out = {"workload": "large corpus 100000x2000000 r=100 (lognormal lengths median 92, cap 2000, Zipf(1.1) words, "
-                       "1+Geometric(0.6) counts)",
-           "n": prob.n, "m": prob.m, "r": prob.r, "nnz": prob.nnz, "longest_row": int(R.max()),
-           "float32_tiles": res[0], "bf16_tiles": res[1],
-           "bf16_objective_rel_diff": abs(res[1]["objective"] - res[0]["objective"]) / res[0]["objective"],
-           "sampled_parity_first_sweep": {"F_rel": rel(Fg[cols], Fo), "cols": int(cols.size),
-                                          "W_rel": rel(Wg[rows], Wo), "rows": int(rows.size),
-                                          "heaviest_rows": [int(R[i]) for i in heavy]}}
-    print(json.dumps(out), flush=True)
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        Fo = np.array(list(ex.map(lambda j: oracle.alg2(prob.csc_idx[prob.csc_ptr[j]:prob.csc_ptr[j + 1]],
+                                                        prob.csc_val[prob.csc_ptr[j]:prob.csc_ptr[j + 1]], W0, sumW,
+                                                        F0[j], ids)[0], cols)))
+        Wo = np.array(list(ex.map(lambda i: oracle.alg2(prob.csr_idx[prob.csr_ptr[i]:prob.csr_ptr[i + 1]],
+                                                        prob.csr_val[prob.csr_ptr[i]:prob.csr_ptr[i + 1]], F1, sumF,
+                                                        W0[i], ids)[0], rows)))
+
+    def rowmax(g, o):
+        e = np.linalg.norm(g.astype(np.float64) - o, axis=1) / np.maximum(np.linalg.norm(o, axis=1), 1e-300)
+        return float(f"{e.max():.2e}")
+
+    rel = lambda a, b: float(f"{np.linalg.norm(a.astype(np.float64) - b) / np.linalg.norm(b):.2e}")
+    return {"workload": "large corpus 100000x2000000 r=100 (lognormal lengths median 92, cap 2000, Zipf(1.1) words, "
+                        "1+Geometric(0.6) counts)",
+            "n": prob.n, "m": prob.m, "r": prob.r, "nnz": prob.nnz, "longest_row": int(R.max()),
+            "timed": f"iterations 2..{sweeps} (sums + both halves, no objective) after the first",
+            "float32_tiles": res[0], "bf16_tiles": res[1],
+            "bf16_objective_rel_diff": float(f"{abs(res[1]['objective'] - res[0]['objective']) / res[0]['objective']:.2e}"),
+            "sampled_parity_first_sweep": {"F_rel": rel(Fg[cols], Fo), "F_col_rel_max": rowmax(Fg[cols], Fo),
+                                           "cols": int(cols.size),
+                                           "W_rel": rel(Wg[rows], Wo), "W_row_rel_max": rowmax(Wg[rows], Wo),
+                                           "rows": int(rows.size),
+                                           "heaviest_rows": [int(R[i]) for i in heavy]}}
+
+
+def large_run(args, log):
+    """bench.py --large: the large-corpus leg alone."""
+    prob = large_problem(args, log)
+    import torch
+    import paper_1604_04026_amd as P
+    torch.cuda.set_device(0)
+    print(json.dumps(large_leg(P, prob, args, log)), flush=True)
 
 
 def ablation_run(args, log):
@@ -562,6 +592,7 @@ def main():
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--traffic-run", action="store_true",
                     help="the command profiled for HBM traffic (calibration copy + sweeps only)")
+    ap.add_argument("--no-large", action="store_true", help="skip the large-corpus leg of the default run")
     ap.add_argument("--large", action="store_true",
                     help="the large corpus (100,000 x 2,000,000, r = 100): float32 vs bf16 tiles")
     ap.add_argument("--out-of-core", action="store_true",
@@ -610,11 +641,13 @@ def main():
         serving = (W, arrivals, sptr, sidx, sval)
         log(f"[bench] {args.serving_requests} serving requests generated ({time.perf_counter() - t0:.1f} s)")
 
+    large = None if args.no_large else large_problem(args, log)
+
     import torch
     import paper_1604_04026_amd as P
     torch.cuda.set_device(0)
 
-    elapsed, tim, D_warm, sweep_ms, warm_factors = sweep_leg(P, prob, args, log)
+    elapsed, tim, D_warm, sweep_ms, warm_factors, final = sweep_leg(P, prob, args, log)
     updates = 2.0 * prob.nnz * prob.r * args.steps
     kernels = {}
     for name, k in tim.items():
@@ -624,16 +657,37 @@ def main():
         kernels[name] = {"kernel": KERNEL_NAMES[name], "ms_per_launch": round(ms, 5),
                          "launches": int(k["launches"]), "gather_bytes": k["gather_bytes"],
                          "gather_GBps": round(k["gather_bytes"] / (ms * 1e-3) / 1e9, 1) if ms > 0 else None}
-    # the dominant launch group among single-dispatch groups (one kernel dispatch per launch)
-    single = {g: v for g, v in kernels.items() if not g.startswith("long")}
-    dom = max(single, key=lambda g: single[g]["ms_per_launch"] * single[g]["launches"])
-    dk = kernels[dom]
-    achieved = dk["gather_bytes"] / (dk["ms_per_launch"] * 1e-3) / 1e9
-    traffic = traffic_for(dom)
-    roofline = {"bound": "hbm", "kernel": f"{dk['kernel']} ({dom})", "achieved": round(achieved, 1),
+    # Roofline under the gather model.  The dominant kernel is the one with the most time per
+    # step over all its launch groups (the long-segment groups included); its achieved rate is
+    # its algorithmic bytes per launch over its average launch duration.  Every launch group's
+    # fraction and the whole step's (all bytes of a step over ms_per_step) are reported beside it.
+    per_kernel = collections.defaultdict(lambda: {"bytes": 0.0, "ms": 0.0, "launches": 0, "groups": []})
+    for g, k in kernels.items():
+        pk = per_kernel[k["kernel"]]
+        pk["bytes"] += k["gather_bytes"] * k["launches"]
+        pk["ms"] += k["ms_per_launch"] * k["launches"]
+        pk["launches"] += k["launches"]
+        pk["groups"].append(g)
+    dname = max(per_kernel, key=lambda n: per_kernel[n]["ms"])
+    dk = per_kernel[dname]
+    achieved = dk["bytes"] / (dk["ms"] * 1e-3) / 1e9
+    tr = [traffic_for(g) for g in dk["groups"]]
+    traffic = (sum(tr) / len(tr)) if all(x is not None for x in tr) else None
+    vb = [valu_busy_for(g) for g in dk["groups"]]
+    valu = (round(sum(v * kernels[g]["ms_per_launch"] for v, g in zip(vb, dk["groups"])) /
+                  sum(kernels[g]["ms_per_launch"] for g in dk["groups"]), 1)
+            if all(v is not None for v in vb) else None)
+    step_bytes = sum(k["gather_bytes"] * k["launches"] for k in kernels.values()) / args.steps
+    step_ms = elapsed * 1e3 / args.steps
+    roofline = {"bound": "hbm", "kernel": f"{dname} ({' + '.join(dk['groups'])})", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "valu_busy_pct": valu_busy_for(dom),
-                "bytes_model": "gather model: per nonzero 8 + 4r, per segment 8 + 8r"}
+                "traffic": traffic, "valu_busy_pct": valu,
+                "bytes_model": "gather model: per nonzero 8 + 4r, per segment 8 + 8r",
+                "step": {"gather_bytes": step_bytes, "ms": round(step_ms, 4),
+                         "achieved_GBps": round(step_bytes / (step_ms * 1e-3) / 1e9, 1),
+                         "frac": round(step_bytes / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+                "groups": {g: {"frac": round(k["gather_GBps"] / HBM_PEAK_GBS, 4), "ms": k["ms_per_launch"],
+                               "valu_busy_pct": valu_busy_for(g)} for g, k in kernels.items()}}
 
     out = {
         "metric": "nnz·r CD updates/sec per sweep",
@@ -665,17 +719,37 @@ def main():
         W, arrivals, sptr, sidx, sval = serving
         out["serving"] = serving_leg(P, W, arrivals, sptr, sidx, sval, args.plain_window, log)
     if not args.no_cpu_baseline:
-        base, D_orc, orc_factors = cpu_baseline(prob, args.cpu_seconds, keep=len(D_warm))
+        import numpy as np
+        n_all = args.warmup + args.steps
+        base, D_orc, kept = cpu_baseline(prob, args.cpu_seconds, keep=(args.warmup, n_all), min_sweeps=n_all)
         out["cpu_baseline"] = base
         n_cmp = min(len(D_orc), len(D_warm))
         rel = [abs(D_warm[i] - D_orc[i]) / D_orc[i] for i in range(n_cmp)]
-        out["check"] = {"sweeps_compared": n_cmp, "objective_rel_err_vs_oracle": [float(f"{x:.2e}") for x in rel]}
-        if orc_factors is not None and n_cmp == len(D_warm):
-            import numpy as np
+        check = {"sweeps_compared": n_cmp, "objective_rel_err_vs_oracle": [float(f"{x:.2e}") for x in rel]}
+
+        def factor_errors(gpu, orc):
             fe = {}
-            for name, g, o in (("W", warm_factors[0], orc_factors[0]), ("F", warm_factors[1], orc_factors[1])):
-                fe[name] = float(f"{np.linalg.norm(g.astype(np.float64) - o) / np.linalg.norm(o):.2e}")
-            out["check"]["factor_rel_err_vs_oracle"] = fe
+            for name, g, o in (("W", gpu[0], orc[0]), ("F", gpu[1], orc[1])):
+                g = g.astype(np.float64)
+                rows = np.linalg.norm(g - o, axis=1) / np.maximum(np.linalg.norm(o, axis=1), 1e-300)
+                flip = np.any((g == 0) != (o == 0), axis=1)
+                fe[name] = {"rel_frobenius": float(f"{np.linalg.norm(g - o) / np.linalg.norm(o):.2e}"),
+                            "row_rel_max_no_flip": float(f"{rows[~flip].max():.2e}") if (~flip).any() else 0.0,
+                            "rows_over_1e-4": int(np.sum(rows > 1e-4)), "rows_with_zero_flip": int(flip.sum())}
+            return fe
+
+        if args.warmup in kept and n_cmp == len(D_warm):
+            check["factor_rel_err_vs_oracle"] = factor_errors(warm_factors, kept[args.warmup])
+        if n_all in kept and len(D_orc) >= n_all:
+            D_end, D_exact, Wg, Fg = final
+            check["after_all_sweeps"] = {
+                "sweeps": n_all,
+                "objective_rel_err_vs_oracle": float(f"{abs(D_end - D_orc[n_all - 1]) / D_orc[n_all - 1]:.2e}"),
+                "exact_objective_rel_err_vs_oracle": float(f"{abs(D_exact - D_orc[n_all - 1]) / D_orc[n_all - 1]:.2e}"),
+                "factors": factor_errors((Wg, Fg), kept[n_all])}
+        out["check"] = check
+    if large is not None:
+        out["large"] = large_leg(P, large, args, log)
     print(json.dumps(out), flush=True)
 
 
