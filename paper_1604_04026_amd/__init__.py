@@ -7,8 +7,11 @@ or cannot be loaded, every call raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -171,6 +174,10 @@ def load(path: str | None = None):
         if not name.endswith("last_error"):
             getattr(lib, name).restype = ctypes.c_int
     if path is None:
+        if _lib is None:
+            # atexit runs hooks last-in first-out: registered after torch's import, this one
+            # runs before torch's own exit hooks
+            atexit.register(_destroy_live_objects)
         _lib = lib
     return lib
 
@@ -262,21 +269,65 @@ def upload_host_v(prob, device="cuda", W=None, F=None) -> DeviceProblem:
                          d(np.asarray(prob.F0 if F is None else F, np.float32)), host_v=True)
 
 
-class Handle:
+# Every live native object (handle, model, server, batch), so that they can be destroyed at
+# interpreter exit before torch and the HIP runtime tear down.  A destroy call during the
+# interpreter's own finalisation (from __del__ of an object that outlived the exit hook, or of
+# module globals) could reach HIP after its teardown began; __del__ therefore does nothing once
+# the interpreter is finalising, and the exit hook below has already released what was live.
+_live: "weakref.WeakSet[_Native]" = weakref.WeakSet()
+_EXIT_ORDER = {"nmfkl_server_destroy": 0, "nmfkl_batch_destroy": 1, "nmfkl_destroy": 2,
+               "nmfkl_model_destroy": 3}
+
+
+class _Native:
+    _destroy_fn = ""
+
+    def _register(self):
+        _live.add(self)
+
+    def _release(self):
+        if self._ptr:
+            ptr, self._ptr = self._ptr, None
+            return getattr(load(), self._destroy_fn)(ptr)
+        return NMFKL_OK
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self._release()
+        except Exception:
+            pass
+
+
+def _destroy_live_objects():
+    """Exit hook: synchronise the device, then destroy the live objects (servers before the
+    models they use)."""
+    objs = sorted(list(_live), key=lambda o: _EXIT_ORDER.get(o._destroy_fn, 9))
+    if not objs:
+        return
+    try:
+        import torch
+        if torch.cuda.is_initialized():
+            torch.cuda.synchronize()
+    except Exception:
+        pass
+    for o in objs:
+        try:
+            o._release()
+        except Exception:
+            pass
+
+
+class Handle(_Native):
     """An nmfkl_handle plus references that keep its device tensors alive."""
+    _destroy_fn = "nmfkl_destroy"
 
     def __init__(self, ptr: int, dev: DeviceProblem, stream):
         self._ptr = ptr
         self.dev = dev
         self.stream = stream
-
-    def __del__(self):
-        try:
-            if self._ptr:
-                load().nmfkl_destroy(self._ptr)
-                self._ptr = None
-        except Exception:
-            pass
+        self._register()
 
 
 def nmfkl_create(dev: DeviceProblem, params: NmfklParams | None = None, stream=None) -> Handle:
@@ -357,19 +408,13 @@ def _mcheck(rc, m=None):
         raise NmfklError(rc, msg.decode() if msg else "")
 
 
-class Model:
+class Model(_Native):
     """An nmfkl_model over a resident W (device tensor n x r, kept alive here)."""
+    _destroy_fn = "nmfkl_model_destroy"
 
     def __init__(self, ptr, W, r, stream):
         self._ptr, self.W, self.r, self.stream = ptr, W, r, stream
-
-    def __del__(self):
-        try:
-            if self._ptr:
-                load().nmfkl_model_destroy(self._ptr)
-                self._ptr = None
-        except Exception:
-            pass
+        self._register()
 
 
 def nmfkl_model_create(W, params: NmfklParams | None = None, stream=None) -> Model:
@@ -433,17 +478,13 @@ def _scheck(rc, s=None):
         raise NmfklError(rc, msg.decode() if msg else "")
 
 
-class Server:
+class Server(_Native):
+    """An nmfkl_server over a model (kept alive here)."""
+    _destroy_fn = "nmfkl_server_destroy"
+
     def __init__(self, ptr, model):
         self._ptr, self.model = ptr, model
-
-    def __del__(self):
-        try:
-            if self._ptr:
-                load().nmfkl_server_destroy(self._ptr)
-                self._ptr = None
-        except Exception:
-            pass
+        self._register()
 
 
 def nmfkl_server_create(m: Model, mem_budget_bytes: int, lanes: int = 8, lane_docs: int = 256) -> Server:
@@ -511,19 +552,13 @@ def _bcheck(rc, b=None):
         raise NmfklError(rc, msg.decode() if msg else "")
 
 
-class Batch:
+class Batch(_Native):
     """An nmfkl_batch over device problems (kept alive here)."""
+    _destroy_fn = "nmfkl_batch_destroy"
 
     def __init__(self, ptr, devs, stream):
         self._ptr, self.devs, self.stream = ptr, devs, stream
-
-    def __del__(self):
-        try:
-            if self._ptr:
-                load().nmfkl_batch_destroy(self._ptr)
-                self._ptr = None
-        except Exception:
-            pass
+        self._register()
 
 
 def nmfkl_batch_create(devs, params: NmfklParams | None = None, stream=None) -> Batch:

@@ -479,6 +479,10 @@ void make_args(nmfkl_handle* h, SweepArgs (&args)[kNumArgs]) {
     args[kArgFfromCsc].Min = h->Mcsc; args[kArgFfromCsc].Mmap = nullptr; args[kArgFfromCsc].Mout = h->Mcsc;
     args[kArgWfromCsc].Min = h->Mcsc; args[kArgWfromCsc].Mmap = h->csr2csc; args[kArgWfromCsc].Mout = h->Mcsr;
     args[kArgWfromCsr].Min = h->Mcsr; args[kArgWfromCsr].Mmap = nullptr; args[kArgWfromCsr].Mout = h->Mcsr;
+    // bf16 tiles: every segment computes its model values from the rounded tiles, so none are
+    // carried (the objective then evaluates eq. 1 from W and F)
+    if (h->prm.tile_bf16)
+        for (auto& a : args) a.Mout = nullptr;
 }
 
 // Permute jobs of the handle: the two halves' fixed factors in the order of (seed, t), and W
@@ -639,7 +643,7 @@ int half_sweep(nmfkl_handle* h, int32_t t, bool fhalf) {
     HIP_TRY(h, enqueue_plan(plan, h->argtab + ai, h->coop_words, h->dev_err, true,
                             (h->prm.tuning & 1) != 0, h->prm.collect_stats != 0, h->stream, h,
                             fhalf ? NMFKL_T_LONG_F : NMFKL_T_LONG_W, fhalf ? NMFKL_T_FUSED_F : NMFKL_T_FUSED_W, ts));
-    h->model = fhalf ? kModelCsc : kModelCsr;
+    h->model = h->prm.tile_bf16 ? kModelNone : (fhalf ? kModelCsc : kModelCsr);
     return NMFKL_OK;
 }
 
@@ -1453,7 +1457,7 @@ int nmfkl_batch_run(nmfkl_batch* b, int32_t t0, int32_t nsweeps) {
     }
     BHIP(b, launch_set_i64(b->t_dev, t0, b->stream));
     BHIP(b, hipGraphLaunch(exec, b->stream));
-    for (nmfkl_handle* h : b->hs) h->model = kModelCsr;
+    for (nmfkl_handle* h : b->hs) h->model = h->prm.tile_bf16 ? kModelNone : kModelCsr;
     return NMFKL_OK;
 }
 
