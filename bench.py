@@ -252,7 +252,7 @@ def serving_leg(P, W, arrivals, ptr, idx, val, window_s, log):
         while waiting:
             d = waiting[0]
             try:
-                if P.nmfkl_server_submit(srv, d, *doc(d)) != 0:
+                if P.nmfkl_server_submit(srv, d, *doc(d)) != 0:    # memory budget or waiting slots full
                     deferred[d] = True
                     break
             except P.NmfklError:

@@ -297,11 +297,17 @@ int nmfkl_batch_destroy(nmfkl_batch* b);
  * are supported (NMFKL_E_UNSUPPORTED beyond). */
 typedef struct nmfkl_result {
     uint64_t req_id;
-    int32_t passes;     /* passes run */
+    int32_t passes;     /* passes run (0 unless status is NMFKL_OK) */
+    int32_t status;     /* NMFKL_OK: folded in; NMFKL_RESULT_EXPIRED: not launched within its
+                           time limit; NMFKL_RESULT_CANCELLED: withdrawn by nmfkl_server_cancel
+                           (kl and f are 0 then) */
     double kl;          /* final KL of the document */
-    double t_submit;    /* steady-clock seconds at submit */
+    double t_submit;    /* steady-clock seconds at submit (nmfkl_server_now's clock) */
     double t_done;      /* steady-clock seconds when the host observed completion */
 } nmfkl_result;
+
+#define NMFKL_RESULT_EXPIRED 1
+#define NMFKL_RESULT_CANCELLED 2
 
 typedef struct nmfkl_server nmfkl_server;
 
@@ -341,20 +347,34 @@ int nmfkl_model_destroy(nmfkl_model* m);
 /* Continuously batched fold-in server over a model.  `lanes` streams each run one batch of
  * up to lane_docs documents at a time; whenever a lane is free, nmfkl_server_poll launches
  * the oldest waiting documents on it, so documents that arrive while others are on the GPU
- * start without waiting for them.  Admission is by memory: the words of all submitted and
- * unfinished documents stay within mem_budget_bytes (8 bytes per word). */
+ * start without waiting for them.  Each document is returned as soon as it has converged:
+ * the kernels write its result into host-coherent memory and then mark it done, so a
+ * document does not wait for the slowest one of its batch.  Admission: the words of all
+ * submitted and unreturned documents stay within mem_budget_bytes (8 bytes per word), and
+ * at most max_queued documents wait for a lane (0: no limit). */
 int nmfkl_server_create(nmfkl_model* m, int64_t mem_budget_bytes, int32_t lanes, int32_t lane_docs,
-                        nmfkl_server** out);
+                        int32_t max_queued, nmfkl_server** out);
 
-/* Submit one document (host arrays, copied before returning).  NMFKL_E_NOMEM: the memory
- * budget is full now (retry later); NMFKL_E_INVAL: malformed; NMFKL_E_UNSUPPORTED: too long. */
+/* Submit one document (host arrays, copied before returning).  timeout_s > 0: if it has not
+ * been launched timeout_s seconds after submission it is not launched and is returned with
+ * status NMFKL_RESULT_EXPIRED (<= 0: no limit).  NMFKL_E_BUSY: max_queued documents are
+ * waiting (retry later); NMFKL_E_NOMEM: the memory budget is full now (retry later);
+ * NMFKL_E_INVAL: malformed; NMFKL_E_UNSUPPORTED: too long. */
 int nmfkl_server_submit(nmfkl_server* s, uint64_t req_id, int32_t L, const int32_t* word_idx,
-                        const float* counts);
+                        const float* counts, double timeout_s);
 
-/* Non-blocking: collect finished batches, launch waiting documents on free lanes, and return
- * up to max_results finished documents (out[k] and f_out[k*r .. k*r+r)). */
+/* Withdraw a document that is still waiting for a lane: it is returned by a later poll with
+ * status NMFKL_RESULT_CANCELLED.  NMFKL_E_INVAL if no waiting document has this id (already
+ * launched, returned or unknown; a launched document runs to the end). */
+int nmfkl_server_cancel(nmfkl_server* s, uint64_t req_id);
+
+/* Non-blocking: collect finished documents, launch waiting documents on free lanes, and
+ * return up to max_results finished documents (out[k] and f_out[k*r .. k*r+r)). */
 int nmfkl_server_poll(nmfkl_server* s, int32_t max_results, nmfkl_result* out, float* f_out,
                       int32_t* n_out);
+
+/* The server's clock (steady-clock seconds, as in t_submit and t_done). */
+int nmfkl_server_now(double* t_out);
 
 /* Documents submitted and not yet returned by poll, and words held against the budget. */
 int nmfkl_server_pending(nmfkl_server* s, int64_t* queued, int64_t* in_flight_words);

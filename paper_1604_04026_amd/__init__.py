@@ -36,7 +36,8 @@ EXPORTED_SYMBOLS = [
     "nmfkl_reset_timings", "nmfkl_destroy", "nmfkl_last_error",
     "nmfkl_model_create", "nmfkl_foldin", "nmfkl_foldin_noalloc", "nmfkl_model_get_stats", "nmfkl_model_last_error",
     "nmfkl_model_destroy", "nmfkl_server_create", "nmfkl_server_submit", "nmfkl_server_poll",
-    "nmfkl_server_pending", "nmfkl_server_last_error", "nmfkl_server_destroy",
+    "nmfkl_server_pending", "nmfkl_server_last_error", "nmfkl_server_destroy", "nmfkl_server_cancel",
+    "nmfkl_server_now",
     "nmfkl_batch_create", "nmfkl_batch_run", "nmfkl_batch_objective", "nmfkl_batch_tune",
     "nmfkl_batch_get_info", "nmfkl_batch_last_error", "nmfkl_batch_destroy",
 ]
@@ -114,8 +115,12 @@ class NmfklBatchInfo(ctypes.Structure):
 
 
 class NmfklResult(ctypes.Structure):
-    _fields_ = [("req_id", ctypes.c_uint64), ("passes", ctypes.c_int32), ("kl", ctypes.c_double),
-                ("t_submit", ctypes.c_double), ("t_done", ctypes.c_double)]
+    _fields_ = [("req_id", ctypes.c_uint64), ("passes", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("kl", ctypes.c_double), ("t_submit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+RESULT_EXPIRED = 1
+RESULT_CANCELLED = 2
 
 
 _lib = None
@@ -155,8 +160,10 @@ def load(path: str | None = None):
     lib.nmfkl_foldin_noalloc.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
     lib.nmfkl_model_get_stats.argtypes = [vp, ctypes.POINTER(NmfklStats)]
     lib.nmfkl_model_destroy.argtypes = [vp]
-    lib.nmfkl_server_create.argtypes = [vp, i64, i32, i32, ctypes.POINTER(vp)]
-    lib.nmfkl_server_submit.argtypes = [vp, u64, i32, vp, vp]
+    lib.nmfkl_server_create.argtypes = [vp, i64, i32, i32, i32, ctypes.POINTER(vp)]
+    lib.nmfkl_server_submit.argtypes = [vp, u64, i32, vp, vp, ctypes.c_double]
+    lib.nmfkl_server_cancel.argtypes = [vp, u64]
+    lib.nmfkl_server_now.argtypes = [ctypes.POINTER(ctypes.c_double)]
     lib.nmfkl_server_poll.argtypes = [vp, i32, ctypes.POINTER(NmfklResult), vp, ctypes.POINTER(ctypes.c_int32)]
     lib.nmfkl_server_pending.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     lib.nmfkl_server_destroy.argtypes = [vp]
@@ -487,31 +494,48 @@ class Server(_Native):
         self._register()
 
 
-def nmfkl_server_create(m: Model, mem_budget_bytes: int, lanes: int = 8, lane_docs: int = 256) -> Server:
+def nmfkl_server_create(m: Model, mem_budget_bytes: int, lanes: int = 8, lane_docs: int = 256,
+                        max_queued: int = 0) -> Server:
     out = ctypes.c_void_p()
-    _scheck(load().nmfkl_server_create(m._ptr, int(mem_budget_bytes), int(lanes), int(lane_docs),
+    _scheck(load().nmfkl_server_create(m._ptr, int(mem_budget_bytes), int(lanes), int(lane_docs), int(max_queued),
                                        ctypes.byref(out)))
     return Server(out.value, m)
 
 
-def nmfkl_server_submit(s: Server, req_id: int, word_idx: np.ndarray, counts: np.ndarray) -> int:
-    """Returns NMFKL_OK, or the admission code (NMFKL_E_NOMEM) when the budget is full now."""
+def nmfkl_server_submit(s: Server, req_id: int, word_idx: np.ndarray, counts: np.ndarray,
+                        timeout_s: float = 0.0) -> int:
+    """Returns NMFKL_OK, or an admission code when the document cannot wait now: NMFKL_E_NOMEM
+    (the memory budget is full) or NMFKL_E_BUSY (every waiting slot is taken).  Raises on
+    malformed or unsupported documents."""
     idx = np.ascontiguousarray(word_idx, dtype=np.int32)
     val = np.ascontiguousarray(counts, dtype=np.float32)
-    rc = load().nmfkl_server_submit(s._ptr, int(req_id), int(idx.size), idx.ctypes.data, val.ctypes.data)
-    if rc not in (NMFKL_OK, -2):
+    rc = load().nmfkl_server_submit(s._ptr, int(req_id), int(idx.size), idx.ctypes.data, val.ctypes.data,
+                                    float(timeout_s))
+    if rc not in (NMFKL_OK, -2, -5):
         _scheck(rc, s._ptr)
     return rc
 
 
+def nmfkl_server_cancel(s: Server, req_id: int) -> int:
+    """Withdraws a waiting document (returned later with status RESULT_CANCELLED); returns
+    NMFKL_OK, or NMFKL_E_INVAL when no waiting document has this id."""
+    return load().nmfkl_server_cancel(s._ptr, int(req_id))
+
+
+def nmfkl_server_now() -> float:
+    t = ctypes.c_double()
+    _scheck(load().nmfkl_server_now(ctypes.byref(t)))
+    return t.value
+
+
 def nmfkl_server_poll(s: Server, max_results: int = 4096):
-    """Finished documents: list of (req_id, passes, kl, t_submit, t_done, f)."""
+    """Finished documents: list of (req_id, passes, kl, t_submit, t_done, f, status)."""
     r = s.model.r
-    res = (NmfklResult * max_results)()
-    f = np.empty((max_results, r), dtype=np.float32)
+    res = (NmfklResult * max(max_results, 1))()
+    f = np.empty((max(max_results, 1), r), dtype=np.float32)
     n = ctypes.c_int32()
     _scheck(load().nmfkl_server_poll(s._ptr, max_results, res, f.ctypes.data, ctypes.byref(n)), s._ptr)
-    return [(res[k].req_id, res[k].passes, res[k].kl, res[k].t_submit, res[k].t_done, f[k].copy())
+    return [(res[k].req_id, res[k].passes, res[k].kl, res[k].t_submit, res[k].t_done, f[k].copy(), res[k].status)
             for k in range(n.value)]
 
 

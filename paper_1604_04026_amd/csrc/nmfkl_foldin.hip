@@ -110,11 +110,13 @@ int group_docs(nmfkl_model* m, const std::vector<int64_t>& len, std::vector<int3
 }
 
 // Launch the variants for grouped documents whose lists were uploaded to dev_docs (variant v
-// at offset off[v]).
+// at offset off[v]), shortest documents first: the launches of a stream run one after the
+// other, so the many short documents of a batch finish (and, in the server, come back) before
+// the few long ones have started.
 int launch_grouped(nmfkl_model* m, const FoldinArgs& f, const int32_t* dev_docs, const int off[kFoldinVariants],
                    const int cnt[kFoldinVariants], hipStream_t stream) {
     const SweepArgs a = foldin_sweep_args(m);
-    for (int v = kFoldinVariants - 1; v >= 0; --v)
+    for (int v = 0; v < kFoldinVariants; ++v)
         MHIP(m, launch_foldin(f, a, v, dev_docs + off[v], cnt[v], stream));
     return NMFKL_OK;
 }
@@ -122,15 +124,22 @@ int launch_grouped(nmfkl_model* m, const FoldinArgs& f, const int32_t* dev_docs,
 }  // namespace
 
 // ----------------------------------------------------------------------------- server
+// Each lane is a stream that runs one batch of documents at a time.  Documents are returned
+// one by one as they finish: the fold-in kernels write every document's result straight into
+// host-coherent pinned memory and then set the document's completion word to the batch tag,
+// which the host polls.  A lane takes a new batch once every document of the current one has
+// been returned and the lane's stream is idle.
 struct nmfkl_server {
     nmfkl_model* model = nullptr;
     int64_t budget_words = 0;     // device words (index + count) that may be in flight
     int32_t max_docs = 0;         // documents per lane batch
     int64_t lane_words = 0;       // words per lane batch
+    int32_t max_queued = 0;       // documents that may wait for a lane (0: no limit)
     struct Req {
         uint64_t id;
         int32_t L;
         double t_submit;
+        double expires;            // steady-clock seconds after which it is not launched (0: never)
         std::vector<int32_t> idx;  // host copy of the document (taken at submit)
         std::vector<float> val;
     };
@@ -138,21 +147,26 @@ struct nmfkl_server {
         hipStream_t stream = nullptr;
         hipEvent_t done = nullptr;
         bool busy = false;
+        unsigned tag = 0;           // batch tag written into h_flag by the kernels
         int64_t* d_ptr = nullptr;
         int32_t* d_idx = nullptr;
         float* d_val = nullptr;
-        float* d_F = nullptr;
-        int32_t* d_passes = nullptr;
-        double* d_kl = nullptr;
         int32_t* d_docs = nullptr;
-        int64_t* h_ptr = nullptr;   // pinned staging
+        int64_t* h_ptr = nullptr;   // pinned staging of the batch
         int32_t* h_idx = nullptr;
         float* h_val = nullptr;
         int32_t* h_docs = nullptr;
-        float* h_F = nullptr;
+        float* h_F = nullptr;       // host-coherent outputs, written by the kernels
         int32_t* h_passes = nullptr;
         double* h_kl = nullptr;
+        unsigned* h_flag = nullptr;
+        float* k_F = nullptr;       // the same outputs as device addresses
+        int32_t* k_passes = nullptr;
+        double* k_kl = nullptr;
+        unsigned* k_flag = nullptr;
         std::vector<Req> reqs;
+        std::vector<char> returned;
+        int32_t nreturned = 0;
         int64_t words = 0;
     };
     std::vector<Lane> lanes;
@@ -160,7 +174,7 @@ struct nmfkl_server {
     int64_t words_in_flight = 0;     // pending + launched
     struct Done {
         uint64_t id;
-        int32_t passes;
+        int32_t passes, status;
         double kl, t_submit, t_done;
         std::vector<float> f;
     };
@@ -185,31 +199,64 @@ int sfail(nmfkl_server* s, int code, const std::string& msg) {
 void release_lane(nmfkl_server::Lane& L) {
     auto df = [](void* p) { if (p) (void)hipFree(p); };
     auto hf = [](void* p) { if (p) (void)hipHostFree(p); };
-    df(L.d_ptr); df(L.d_idx); df(L.d_val); df(L.d_F); df(L.d_passes); df(L.d_kl); df(L.d_docs);
-    hf(L.h_ptr); hf(L.h_idx); hf(L.h_val); hf(L.h_docs); hf(L.h_F); hf(L.h_passes); hf(L.h_kl);
+    df(L.d_ptr); df(L.d_idx); df(L.d_val); df(L.d_docs);
+    hf(L.h_ptr); hf(L.h_idx); hf(L.h_val); hf(L.h_docs); hf(L.h_F); hf(L.h_passes); hf(L.h_kl); hf(L.h_flag);
     if (L.done) (void)hipEventDestroy(L.done);
     if (L.stream) (void)hipStreamDestroy(L.stream);
 }
 
-// Collect finished lanes.
+void finish_unlaunched(nmfkl_server* s, nmfkl_server::Req&& q, int status, double t) {
+    nmfkl_server::Done d;
+    d.id = q.id;
+    d.passes = 0;
+    d.status = status;
+    d.kl = 0.0;
+    d.t_submit = q.t_submit;
+    d.t_done = t;
+    d.f.assign((size_t)s->model->r, 0.0f);
+    s->words_in_flight -= q.L;
+    s->done.push_back(std::move(d));
+}
+
+// Return the finished documents of every busy lane; free a lane whose documents are all back.
 int collect(nmfkl_server* s) {
     const int r = s->model->r;
     for (auto& L : s->lanes) {
         if (!L.busy) continue;
-        const hipError_t q = hipEventQuery(L.done);
-        if (q == hipErrorNotReady) continue;
-        if (q != hipSuccess) return sfail(s, NMFKL_E_DEVICE, std::string("lane: ") + hipGetErrorString(q));
-        const double t = now_seconds();
-        for (size_t i = 0; i < L.reqs.size(); ++i) {
+        const int nd = (int)L.reqs.size();
+        double t = 0.0;
+        for (int i = 0; i < nd; ++i) {
+            if (L.returned[i]) continue;
+            if (__atomic_load_n(L.h_flag + i, __ATOMIC_ACQUIRE) != L.tag) continue;
+            if (t == 0.0) t = now_seconds();
             nmfkl_server::Done d;
             d.id = L.reqs[i].id;
             d.passes = L.h_passes[i];
+            d.status = NMFKL_OK;
             d.kl = L.h_kl[i];
             d.t_submit = L.reqs[i].t_submit;
             d.t_done = t;
             d.f.assign(L.h_F + (size_t)i * r, L.h_F + (size_t)(i + 1) * r);
             s->done.push_back(std::move(d));
+            L.returned[i] = 1;
+            ++L.nreturned;
         }
+        if (L.nreturned < nd) {
+            // a device error would leave documents unfinished: surface it
+            const hipError_t q = hipEventQuery(L.done);
+            if (q != hipSuccess && q != hipErrorNotReady)
+                return sfail(s, NMFKL_E_DEVICE, std::string("lane: ") + hipGetErrorString(q));
+            if (q == hipSuccess) {
+                // the kernels have ended: every completion word must be set
+                for (int i = 0; i < nd; ++i)
+                    if (!L.returned[i] && __atomic_load_n(L.h_flag + i, __ATOMIC_ACQUIRE) != L.tag)
+                        return sfail(s, NMFKL_E_DEVICE, "lane ended with an unfinished document");
+            }
+            continue;
+        }
+        const hipError_t q = hipEventQuery(L.done);
+        if (q == hipErrorNotReady) continue;
+        if (q != hipSuccess) return sfail(s, NMFKL_E_DEVICE, std::string("lane: ") + hipGetErrorString(q));
         s->words_in_flight -= L.words;
         L.reqs.clear();
         L.words = 0;
@@ -218,9 +265,11 @@ int collect(nmfkl_server* s) {
     return NMFKL_OK;
 }
 
-// Form a batch for every idle lane from the pending queue (FIFO) and launch it.
+// Form a batch for every idle lane from the waiting documents (FIFO; those past their time
+// limit are returned as expired instead) and launch it.
 int dispatch(nmfkl_server* s) {
     nmfkl_model* m = s->model;
+    double t = 0.0;
     for (auto& L : s->lanes) {
         if (L.busy || s->pending.empty()) continue;
         int nd = 0;
@@ -229,6 +278,13 @@ int dispatch(nmfkl_server* s) {
         while (!s->pending.empty() && nd < s->max_docs && w + s->pending.front().L <= s->lane_words) {
             nmfkl_server::Req q = std::move(s->pending.front());
             s->pending.pop_front();
+            if (q.expires > 0.0) {
+                if (t == 0.0) t = now_seconds();
+                if (t > q.expires) {
+                    finish_unlaunched(s, std::move(q), NMFKL_RESULT_EXPIRED, t);
+                    continue;
+                }
+            }
             std::memcpy(L.h_idx + w, q.idx.data(), (size_t)q.L * sizeof(int32_t));
             std::memcpy(L.h_val + w, q.val.data(), (size_t)q.L * sizeof(float));
             w += q.L;
@@ -249,17 +305,20 @@ int dispatch(nmfkl_server* s) {
             std::memcpy(L.h_docs + pos, lists[v].data(), lists[v].size() * sizeof(int32_t));
             pos += cnt[v];
         }
+        L.tag += 1u;
+        if (L.tag == 0u) L.tag = 1u;   // 0 is the words' initial value
         SHIP(s, hipMemcpyAsync(L.d_ptr, L.h_ptr, (size_t)(nd + 1) * sizeof(int64_t), hipMemcpyHostToDevice, L.stream));
         SHIP(s, hipMemcpyAsync(L.d_idx, L.h_idx, (size_t)w * sizeof(int32_t), hipMemcpyHostToDevice, L.stream));
         SHIP(s, hipMemcpyAsync(L.d_val, L.h_val, (size_t)w * sizeof(float), hipMemcpyHostToDevice, L.stream));
         SHIP(s, hipMemcpyAsync(L.d_docs, L.h_docs, (size_t)pos * sizeof(int32_t), hipMemcpyHostToDevice, L.stream));
-        const FoldinArgs f = foldin_args(m, L.d_ptr, L.d_idx, L.d_val, L.d_F, L.d_passes, L.d_kl);
+        FoldinArgs f = foldin_args(m, L.d_ptr, L.d_idx, L.d_val, L.k_F, L.k_passes, L.k_kl);
+        f.done = L.k_flag;
+        f.done_tag = L.tag;
         const int rc = launch_grouped(m, f, L.d_docs, off, cnt, L.stream);
         if (rc) return sfail(s, rc, m->err);
-        SHIP(s, hipMemcpyAsync(L.h_F, L.d_F, (size_t)nd * m->r * sizeof(float), hipMemcpyDeviceToHost, L.stream));
-        SHIP(s, hipMemcpyAsync(L.h_passes, L.d_passes, (size_t)nd * sizeof(int32_t), hipMemcpyDeviceToHost, L.stream));
-        SHIP(s, hipMemcpyAsync(L.h_kl, L.d_kl, (size_t)nd * sizeof(double), hipMemcpyDeviceToHost, L.stream));
         SHIP(s, hipEventRecord(L.done, L.stream));
+        L.returned.assign((size_t)nd, 0);
+        L.nreturned = 0;
         L.words = w;
         L.busy = true;
     }
@@ -432,12 +491,13 @@ int nmfkl_model_destroy(nmfkl_model* m) {
 
 // ---------------------------------------------------------------------------- server
 int nmfkl_server_create(nmfkl_model* m, int64_t mem_budget_bytes, int32_t lanes, int32_t lane_docs,
-                        nmfkl_server** out) {
+                        int32_t max_queued, nmfkl_server** out) {
     if (!out) return sfail(nullptr, NMFKL_E_INVAL, "out is null");
     *out = nullptr;
     if (!m) return sfail(nullptr, NMFKL_E_INVAL, "null model");
     if (lanes < 1 || lanes > 64) return sfail(nullptr, NMFKL_E_INVAL, "lanes must be in [1, 64]");
     if (lane_docs < 1) return sfail(nullptr, NMFKL_E_INVAL, "lane_docs must be >= 1");
+    if (max_queued < 0) return sfail(nullptr, NMFKL_E_INVAL, "max_queued must be >= 0");
     const int64_t bytes_per_word = (int64_t)(sizeof(int32_t) + sizeof(float));
     const int64_t max_doc_words = kFoldinCapacity[kFoldinVariants - 1];
     if (mem_budget_bytes < max_doc_words * bytes_per_word)
@@ -447,6 +507,7 @@ int nmfkl_server_create(nmfkl_model* m, int64_t mem_budget_bytes, int32_t lanes,
     s->model = m;
     s->budget_words = mem_budget_bytes / bytes_per_word;
     s->max_docs = lane_docs;
+    s->max_queued = max_queued;
     s->lane_words = std::max<int64_t>(max_doc_words, s->budget_words / lanes);
     s->lanes.resize(lanes);
     const int r = m->r;
@@ -461,29 +522,37 @@ int nmfkl_server_create(nmfkl_model* m, int64_t mem_budget_bytes, int32_t lanes,
         if ((e = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking)) != hipSuccess) return fail_out(e);
         if ((e = hipEventCreateWithFlags(&L.done, hipEventDisableTiming)) != hipSuccess) return fail_out(e);
         const size_t nd = (size_t)lane_docs, nw = (size_t)s->lane_words;
+        // outputs and completion words: host-coherent pinned memory that the kernels write
+        const unsigned coh = hipHostMallocCoherent | hipHostMallocMapped;
         if ((e = hipMalloc(reinterpret_cast<void**>(&L.d_ptr), (nd + 1) * sizeof(int64_t))) != hipSuccess ||
             (e = hipMalloc(reinterpret_cast<void**>(&L.d_idx), nw * sizeof(int32_t))) != hipSuccess ||
             (e = hipMalloc(reinterpret_cast<void**>(&L.d_val), nw * sizeof(float))) != hipSuccess ||
-            (e = hipMalloc(reinterpret_cast<void**>(&L.d_F), nd * r * sizeof(float))) != hipSuccess ||
-            (e = hipMalloc(reinterpret_cast<void**>(&L.d_passes), nd * sizeof(int32_t))) != hipSuccess ||
-            (e = hipMalloc(reinterpret_cast<void**>(&L.d_kl), nd * sizeof(double))) != hipSuccess ||
             (e = hipMalloc(reinterpret_cast<void**>(&L.d_docs), nd * sizeof(int32_t))) != hipSuccess ||
             (e = hipHostMalloc(reinterpret_cast<void**>(&L.h_ptr), (nd + 1) * sizeof(int64_t), hipHostMallocDefault)) != hipSuccess ||
             (e = hipHostMalloc(reinterpret_cast<void**>(&L.h_idx), nw * sizeof(int32_t), hipHostMallocDefault)) != hipSuccess ||
             (e = hipHostMalloc(reinterpret_cast<void**>(&L.h_val), nw * sizeof(float), hipHostMallocDefault)) != hipSuccess ||
             (e = hipHostMalloc(reinterpret_cast<void**>(&L.h_docs), nd * sizeof(int32_t), hipHostMallocDefault)) != hipSuccess ||
-            (e = hipHostMalloc(reinterpret_cast<void**>(&L.h_F), nd * r * sizeof(float), hipHostMallocDefault)) != hipSuccess ||
-            (e = hipHostMalloc(reinterpret_cast<void**>(&L.h_passes), nd * sizeof(int32_t), hipHostMallocDefault)) != hipSuccess ||
-            (e = hipHostMalloc(reinterpret_cast<void**>(&L.h_kl), nd * sizeof(double), hipHostMallocDefault)) != hipSuccess)
+            (e = hipHostMalloc(reinterpret_cast<void**>(&L.h_F), nd * r * sizeof(float), coh)) != hipSuccess ||
+            (e = hipHostMalloc(reinterpret_cast<void**>(&L.h_passes), nd * sizeof(int32_t), coh)) != hipSuccess ||
+            (e = hipHostMalloc(reinterpret_cast<void**>(&L.h_kl), nd * sizeof(double), coh)) != hipSuccess ||
+            (e = hipHostMalloc(reinterpret_cast<void**>(&L.h_flag), nd * sizeof(unsigned), coh)) != hipSuccess)
+            return fail_out(e);
+        std::memset(L.h_flag, 0, nd * sizeof(unsigned));
+        if ((e = hipHostGetDevicePointer(reinterpret_cast<void**>(&L.k_F), L.h_F, 0)) != hipSuccess ||
+            (e = hipHostGetDevicePointer(reinterpret_cast<void**>(&L.k_passes), L.h_passes, 0)) != hipSuccess ||
+            (e = hipHostGetDevicePointer(reinterpret_cast<void**>(&L.k_kl), L.h_kl, 0)) != hipSuccess ||
+            (e = hipHostGetDevicePointer(reinterpret_cast<void**>(&L.k_flag), L.h_flag, 0)) != hipSuccess)
             return fail_out(e);
     }
     *out = s;
     return NMFKL_OK;
 }
 
-int nmfkl_server_submit(nmfkl_server* s, uint64_t req_id, int32_t L, const int32_t* word_idx, const float* counts) {
+int nmfkl_server_submit(nmfkl_server* s, uint64_t req_id, int32_t L, const int32_t* word_idx, const float* counts,
+                        double timeout_s) {
     if (!s) return sfail(nullptr, NMFKL_E_INVAL, "null server");
     if (L < 0 || (L > 0 && (!word_idx || !counts))) return sfail(s, NMFKL_E_INVAL, "bad document");
+    if (!(timeout_s == timeout_s)) return sfail(s, NMFKL_E_INVAL, "timeout is NaN");
     if (variant_of_length(L) < 0) return sfail(s, NMFKL_E_UNSUPPORTED, "document too long for fold-in");
     const int32_t n = s->model->n;
     for (int32_t l = 0; l < L; ++l) {
@@ -492,16 +561,31 @@ int nmfkl_server_submit(nmfkl_server* s, uint64_t req_id, int32_t L, const int32
         if (!(counts[l] >= 0.0f) || !std::isfinite(counts[l]))
             return sfail(s, NMFKL_E_INVAL, "counts must be finite and >= 0");
     }
+    if (s->max_queued > 0 && (int64_t)s->pending.size() >= s->max_queued)
+        return sfail(s, NMFKL_E_BUSY, "every waiting slot is taken");
     if (s->words_in_flight + L > s->budget_words) return sfail(s, NMFKL_E_NOMEM, "memory budget exhausted");
     nmfkl_server::Req q;
     q.id = req_id;
     q.L = L;
     q.t_submit = now_seconds();
+    q.expires = timeout_s > 0.0 ? q.t_submit + timeout_s : 0.0;
     q.idx.assign(word_idx, word_idx + L);
     q.val.assign(counts, counts + L);
     s->pending.push_back(std::move(q));
     s->words_in_flight += L;
     return NMFKL_OK;
+}
+
+int nmfkl_server_cancel(nmfkl_server* s, uint64_t req_id) {
+    if (!s) return sfail(nullptr, NMFKL_E_INVAL, "null server");
+    for (auto it = s->pending.begin(); it != s->pending.end(); ++it) {
+        if (it->id != req_id) continue;
+        nmfkl_server::Req q = std::move(*it);
+        s->pending.erase(it);
+        finish_unlaunched(s, std::move(q), NMFKL_RESULT_CANCELLED, now_seconds());
+        return NMFKL_OK;
+    }
+    return sfail(s, NMFKL_E_INVAL, "no waiting document has this id (launched, finished or unknown)");
 }
 
 int nmfkl_server_poll(nmfkl_server* s, int32_t max_results, nmfkl_result* out, float* f_out, int32_t* n_out) {
@@ -516,6 +600,7 @@ int nmfkl_server_poll(nmfkl_server* s, int32_t max_results, nmfkl_result* out, f
         const auto& d = s->done.front();
         out[k].req_id = d.id;
         out[k].passes = d.passes;
+        out[k].status = d.status;
         out[k].kl = d.kl;
         out[k].t_submit = d.t_submit;
         out[k].t_done = d.t_done;
@@ -530,9 +615,15 @@ int nmfkl_server_poll(nmfkl_server* s, int32_t max_results, nmfkl_result* out, f
 int nmfkl_server_pending(nmfkl_server* s, int64_t* queued, int64_t* in_flight_words) {
     if (!s) return sfail(nullptr, NMFKL_E_INVAL, "null server");
     int64_t busy = 0;
-    for (auto& L : s->lanes) busy += L.busy ? (int64_t)L.reqs.size() : 0;
+    for (auto& L : s->lanes) busy += L.busy ? (int64_t)(L.reqs.size() - L.nreturned) : 0;
     if (queued) *queued = (int64_t)s->pending.size() + busy + (int64_t)s->done.size();
     if (in_flight_words) *in_flight_words = s->words_in_flight;
+    return NMFKL_OK;
+}
+
+int nmfkl_server_now(double* t_out) {
+    if (!t_out) return NMFKL_E_INVAL;
+    *t_out = now_seconds();
     return NMFKL_OK;
 }
 

@@ -11,6 +11,9 @@ namespace nmfkl {
 // Width of one tile chunk: the number of consecutive (permuted) coordinates whose
 // fixed-factor values a lane holds in registers at a time.
 constexpr int kChunk = 8;
+// Chunk width of the long-segment kernels and of the chunk-major copy they read.
+constexpr int kChunkMajorW = 4;
+static_assert(kChunkMajorW == 2 || kChunkMajorW == 4, "chunk-major copies are allocated for r rounded up to 4");
 
 // Philox-4x64 with 10 rounds (Salmon et al., SC'11), shared by the host permutation entry
 // point and the on-device permutation kernel.
@@ -86,8 +89,8 @@ struct PermJob {
                           //    column sums are those of the rounded values
     int32_t pad;
     float* Apc;           // nullptr, or a second copy in chunk-major order: the values of permuted
-                          // columns 4c..4c+3 of row p at Apc[(c * P + p) * 4 ..] (zero beyond r;
-                          // bfloat16 when bf16)
+                          // columns Wc..Wc+W-1 of row p at Apc[(c * P + p) * W ..], W =
+                          // kChunkMajorW (zero beyond r; bfloat16 when bf16)
 };
 
 // One half-sweep's per-launch arguments (kernels read them from a device table).
@@ -132,6 +135,9 @@ struct FoldinArgs {
     int r;
     int max_passes;
     double tol;
+    unsigned* done;          // nullptr, or per-document completion words (host-coherent memory):
+                             // done[d] = done_tag once F, passes and kl of document d are written
+    unsigned done_tag;
 };
 
 // Fold-in variants: 0: 16 lanes x 4, 1: 64 x 4, 2: 256 x 4, 3: 256 x 8 nonzeros (blocks of

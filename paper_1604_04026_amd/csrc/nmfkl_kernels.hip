@@ -184,15 +184,16 @@ __global__ void __launch_bounds__(256) k_permute_jobs(const PermJob* __restrict_
         __syncthreads();
     }
     if (jb.Apc) {
-        // the chunk-major copy: thread (row group, component q) writes 16 consecutive rows'
-        // 16-byte chunk entries per wave, so the stores are contiguous
-        const int q = threadIdx.x & 3;
+        // the chunk-major copy: thread (row group, component q) writes 256 / kChunkMajorW
+        // consecutive rows' chunk entries per block pass, so the stores are contiguous
+        constexpr int W = kChunkMajorW;
+        const int q = threadIdx.x % W;
         const float* __restrict__ A = jb.A;
-        for (int c = 0; c < Sc / 4; ++c) {
-            const int k = sid[4 * c + q];
-            for (int64_t p = p0 + (threadIdx.x >> 2); p < p1; p += 64) {
+        for (int c = 0; c < Sc / W; ++c) {
+            const int k = sid[W * c + q];
+            for (int64_t p = p0 + (threadIdx.x / W); p < p1; p += 256 / W) {
                 const float a = k >= 0 ? A[p * r + k] : 0.0f;
-                const int64_t pc = ((int64_t)c * jb.P + p) * 4 + q;
+                const int64_t pc = ((int64_t)c * jb.P + p) * W + q;
                 if (jb.bf16) reinterpret_cast<uint16_t*>(jb.Apc)[pc] = bf16_rne(a);
                 else jb.Apc[pc] = a;
             }
@@ -462,10 +463,10 @@ template <int E, int STRIDE, int CW, class St>
 __device__ __forceinline__ void load_chunk(const SweepArgs& a, St& st, int L, int lo,
                                            int lane, int c, float4 (&t)[E][kQuads<CW>]) {
     // (row p, chunk c) starts at element p * rs + c * cs of the copy (uniform strides)
-    const bool cm = CW == 4 && a.Apc != nullptr;
+    const bool cm = CW == kChunkMajorW && a.Apc != nullptr;
     const float* base = cm ? a.Apc : a.Ap;
-    const int64_t cs = cm ? a.Prows * 4 : (int64_t)CW;
-    const int64_t rs = cm ? 4 : (int64_t)a.Sp;
+    const int64_t cs = cm ? a.Prows * kChunkMajorW : (int64_t)CW;
+    const int64_t rs = cm ? kChunkMajorW : (int64_t)a.Sp;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         if (lo + lane + STRIDE * e < L) {
@@ -552,7 +553,13 @@ __device__ __forceinline__ void newton_coordinate(const SweepArgs& a, int s, con
             if (g > 0.0) d = -xk;
             else break;
         } else {
-            const float xn = xk - (float)g / h;
+            // g / h by the reciprocal and one Newton-Raphson correction (within an ulp or two of
+            // the quotient; the IEEE division's scale/fixup sequence is on every step's chain)
+            const float gf = (float)g;
+            const float rh = fast_rcp(h);
+            float q = gf * rh;
+            q = fmaf(fmaf(-h, q, gf), rh, q);
+            const float xn = xk - q;
             d = fmaxf(xn, 0.0f) - xk;
         }
         const float dN = d;  // Alg. 2's projected Newton step (the break test uses it)
@@ -911,8 +918,8 @@ hipError_t launch_sweep_fused(const SweepArgs* tab, const BlockWork* work, const
 // such a launch are co-resident (cooperative launch), so every wait ends.  Counts and ids
 // live in LDS, the model values in registers, w and u are recomputed from the model at each
 // chunk start, and tile chunks are 4 coordinates wide.
-constexpr int kLongCW = 4;
-constexpr int kCoopCW = 4;
+constexpr int kLongCW = kChunkMajorW;
+constexpr int kCoopCW = kChunkMajorW;
 
 // One block's part of a long segment: the segment's x and column sums into LDS, the sweep,
 // and x back (part 0).  COOP: the blocks of the segment exchange through CoopReducer.
@@ -1188,6 +1195,14 @@ __device__ __forceinline__ void foldin_segment(const FoldinArgs& f, const SweepA
     if (lane == 0) {
         f.passes[d] = p;
         f.kl[d] = kl;
+    }
+    if (f.done) {
+        // the document's outputs are visible system-wide before its completion word: every
+        // lane orders its own stores (a wave waits for all of its lanes'), and a multi-wave
+        // document's waves meet at a barrier (the whole block works on that one document)
+        __threadfence_system();
+        if constexpr (G > 64) __syncthreads();
+        if (lane == 0) __hip_atomic_store(f.done + d, f.done_tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
     if (a.stats && lane == 0) {
 #pragma unroll

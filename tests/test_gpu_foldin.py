@@ -139,3 +139,84 @@ def test_long_documents_vs_oracle(small_serving):
     with pytest.raises(P.NmfklError) as ei:
         P.nmfkl_server_submit(srv, 1, too_long, np.ones(too_long.size, np.float32))
     assert ei.value.code == -6
+
+
+def _slow_and_fast(W, seed=21):
+    """One document of 5,000 distinct words (many passes over a 512-lane block) and 50 of one
+    word (one or two passes each)."""
+    n = W.shape[0]
+    g = np.random.default_rng(seed)
+    slow = (np.sort(g.choice(n, 5000, replace=False)).astype(np.int32),
+            (1 + g.geometric(0.3, 5000)).astype(np.float32))
+    fast = [(np.array([w], np.int32), np.array([3.0], np.float32)) for w in g.choice(n, 50, replace=False)]
+    return slow, fast
+
+
+def _drain(srv, want, limit=60.0):
+    out, polls = {}, []
+    t0 = time.time()
+    while len(out) < want:
+        got = P.nmfkl_server_poll(srv, 1024)
+        if got:
+            polls.append([rec[0] for rec in got])
+        for rec in got:
+            out[rec[0]] = rec
+        assert time.time() - t0 < limit
+    return out, polls
+
+
+def test_server_returns_each_document_when_it_finishes(small_serving):
+    """One lane runs one batch: the slow document and 50 one-word documents.  The one-word
+    documents come back before the slow one, in earlier polls, while the lane still runs."""
+    import torch
+    W = small_serving[0]
+    m = P.nmfkl_model_create(torch.from_numpy(W).cuda())
+    srv = P.nmfkl_server_create(m, 64 << 20, lanes=1, lane_docs=64)
+    slow, fast = _slow_and_fast(W)
+    assert P.nmfkl_server_submit(srv, 1000, *slow) == 0
+    for k, d in enumerate(fast):
+        assert P.nmfkl_server_submit(srv, k, *d) == 0
+    out, polls = _drain(srv, 51)
+    assert all(rec[6] == 0 for rec in out.values())
+    assert 1000 not in polls[0], "the slow document came back with the first results"
+    assert max(out[k][4] for k in range(50)) < out[1000][4]
+    print(f"per-document return: {len(polls)} polls returned results; slow document {out[1000][1]} passes, "
+          f"{(out[1000][4] - max(out[k][4] for k in range(50))) * 1e3:.2f} ms after the last one-word document")
+    # and each result equals plain fold-in of the same document
+    dp = torch.tensor([0, slow[0].size], dtype=torch.int64, device="cuda")
+    F, ps, kl = P.nmfkl_foldin(m, dp, torch.from_numpy(slow[0]).cuda(), torch.from_numpy(slow[1]).cuda())
+    assert np.array_equal(F.cpu().numpy()[0], out[1000][5]) and int(ps[0]) == out[1000][1]
+    P.nmfkl_server_destroy(srv)
+    P.nmfkl_model_destroy(m)
+
+
+def test_server_timeout_cancel_and_busy(small_serving):
+    """With the single lane busy: a document whose time limit passes while it waits comes back
+    expired; a waiting document can be cancelled, a launched one cannot; the waiting queue
+    refuses documents beyond max_queued with NMFKL_E_BUSY."""
+    import torch
+    W = small_serving[0]
+    m = P.nmfkl_model_create(torch.from_numpy(W).cuda())
+    srv = P.nmfkl_server_create(m, 64 << 20, lanes=1, lane_docs=64, max_queued=3)
+    slow, fast = _slow_and_fast(W, seed=22)
+    assert P.nmfkl_server_submit(srv, 1000, *slow) == 0
+    assert P.nmfkl_server_poll(srv, 0) == []              # launches the slow document
+    assert P.nmfkl_server_submit(srv, 1, *fast[0], timeout_s=1e-6) == 0
+    assert P.nmfkl_server_submit(srv, 2, *fast[1]) == 0
+    assert P.nmfkl_server_submit(srv, 3, *fast[2]) == 0
+    assert P.nmfkl_server_submit(srv, 4, *fast[3]) == -5     # three are waiting: busy
+    assert P.nmfkl_server_cancel(srv, 2) == 0
+    assert P.nmfkl_server_cancel(srv, 2) == -1               # already withdrawn
+    assert P.nmfkl_server_cancel(srv, 1000) == -1            # launched: runs to the end
+    assert P.nmfkl_server_submit(srv, 4, *fast[3]) == 0      # a slot is free again
+    out, _ = _drain(srv, 5)
+    assert out[1000][6] == 0 and out[3][6] == 0 and out[4][6] == 0
+    assert out[1][6] == P.RESULT_EXPIRED and out[1][1] == 0
+    assert out[2][6] == P.RESULT_CANCELLED and out[2][1] == 0
+    # the words of launched documents are released once their lane is free again
+    t0 = time.time()
+    while P.nmfkl_server_pending(srv) != (0, 0):
+        assert P.nmfkl_server_poll(srv, 8) == []
+        assert time.time() - t0 < 10
+    P.nmfkl_server_destroy(srv)
+    P.nmfkl_model_destroy(m)
