@@ -155,8 +155,9 @@ struct BlockWork {
 
 // The (G lanes per segment, E elements per lane) variants of the fused launch.
 struct Variant { int G, E; };
-constexpr int kNumVariants = 6;
-constexpr Variant kVariants[kNumVariants] = {{8, 4}, {16, 4}, {32, 4}, {64, 4}, {64, 8}, {256, 4}};
+constexpr int kNumVariants = 10;
+constexpr Variant kVariants[kNumVariants] = {{8, 4},  {16, 4}, {32, 3}, {32, 4},  {64, 3},
+                                             {64, 4}, {64, 6}, {64, 8}, {256, 3}, {256, 4}};
 constexpr int kFusedThreads = 256;
 constexpr int kMaxFusedLength = 1024;   // 256 * 4
 
