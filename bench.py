@@ -350,6 +350,66 @@ def _counter_rows(path):
         return list(csv.DictReader(fh))
 
 
+GROUP_NAMES = ("fused_F", "fused_W", "long_F", "long_W", "terms")
+
+
+def launch_groups(rows):
+    """Per-dispatch values (dispatch id, kernel name, grid, value) of a --traffic-run ->
+    per-launch-group values of the sweeps after the warm-up sweep.  In each half the
+    long-segment launches are enqueued before the binned launch, and the binned launches
+    alternate F-half, W-half; so a half's long-segment dispatches are those since the previous
+    binned dispatch, and the objective's terms follow the W-half.  A group's value per sweep is
+    the sum over its dispatches."""
+    sweeps, pending_long, nfused = [], 0.0, 0
+    for _, name, _, v in sorted(rows):
+        if "k_sweep_long" in name:
+            pending_long += v
+        elif "k_sweep_fused" in name:
+            half = "F" if nfused % 2 == 0 else "W"
+            if half == "F":
+                sweeps.append({g: 0.0 for g in GROUP_NAMES})
+            sweeps[-1]["fused_" + half] += v
+            sweeps[-1]["long_" + half] += pending_long
+            pending_long = 0.0
+            nfused += 1
+        elif "k_model_terms" in name and sweeps:
+            sweeps[-1]["terms"] += v
+    sweeps = sweeps[1:]      # the warm-up sweep (first model pass, first touches)
+    return {g: [sw[g] for sw in sweeps if sw[g] > 0] for g in GROUP_NAMES}
+
+
+def valu_summarize(valu_dir, out_path):
+    """VALUBusy and VALUUtilization (rocprofv3 derived counters, %) of each launch group of a
+    --traffic-run, averaged over the sweeps after the warm-up sweep (a group of several
+    dispatches: weighted by dispatch duration)."""
+    rows = [r for r in _counter_rows(valu_dir)]
+    per = collections.defaultdict(dict)
+    meta = {}
+    for r in rows:
+        d = int(r["Dispatch_Id"])
+        per[d][r["Counter_Name"]] = float(r["Counter_Value"])
+        meta[d] = (r["Kernel_Name"], int(r.get("End_Timestamp", 0) or 0) - int(r.get("Start_Timestamp", 0) or 0))
+    out_groups = {}
+    for counter in ("VALUBusy", "VALUUtilization"):
+        vals = [(d, meta[d][0], meta[d][1], per[d].get(counter, 0.0) * max(meta[d][1], 1)) for d in sorted(per)]
+        durs = [(d, meta[d][0], meta[d][1], float(max(meta[d][1], 1))) for d in sorted(per)]
+        num, den = launch_groups(vals), launch_groups(durs)
+        for g in GROUP_NAMES:
+            if num[g] and den[g]:
+                out_groups.setdefault(g, {})[counter] = round(sum(num[g]) / sum(den[g]), 1)
+    out = {"kernel_source_sha256_16": source_hash(),
+           "counter": "rocprofv3 derived VALUBusy (100 * SQ_ACTIVE_INST_VALU / CU_NUM / GRBM_GUI_ACTIVE) and "
+                      "VALUUtilization, per launch group, duration-weighted over the sweeps after the warm-up sweep of "
+                      "bench.py --traffic-run --steps 3",
+           "groups": {g: v["VALUBusy"] for g, v in out_groups.items() if "VALUBusy" in v},
+           "utilization": {g: v.get("VALUUtilization") for g, v in out_groups.items()},
+           "command": "rocprofv3 --pmc VALUBusy VALUUtilization -d <dir> -o run --output-format csv -- "
+                      "python3 bench.py --traffic-run --steps 3; python3 bench.py --valu-summarize <dir> profiles/valu.json"}
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def traffic_summarize(fetch_dir, write_dir, out_path):
     """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the traffic run -> bytes per launch of
     each launch group, scaled by what the counters read for the calibration copy."""
@@ -370,14 +430,11 @@ def traffic_summarize(fetch_dir, write_dir, out_path):
         if not copies:
             raise SystemExit(f"{counter}: calibration copy not found")
         scale = (COPY_BYTES / 1024) / (sum(copies[1:] or copies) / len(copies[1:] or copies))
-        fused = [v for _, name, _, v in rows if "k_sweep_fused" in name]
-        model = [v for _, name, _, v in rows if "k_model_terms" in name]
-        # every sweep launches the F-half binned kernel, then the W-half one; skip the warm-up sweep
-        groups = {"fused_F": fused[2::2], "fused_W": fused[3::2], "terms": model[1:]}
+        groups = launch_groups(rows)
         res[counter] = {"scale": scale, "copy_kib": copies,
                         "groups": {g: (sum(v) / len(v) * 1024 * scale if v else None) for g, v in groups.items()}}
     groups = {}
-    for g in ("fused_F", "fused_W", "terms"):
+    for g in GROUP_NAMES:
         f, w = res["FETCH_SIZE"]["groups"][g], res["WRITE_SIZE"]["groups"][g]
         groups[g] = {"fetch_bytes_per_launch": f, "write_bytes_per_launch": w,
                      "hbm_bytes_per_launch": (f + w) if f is not None and w is not None else None}
@@ -575,6 +632,9 @@ def main():
     if len(sys.argv) >= 2 and sys.argv[1] == "--traffic-summarize":
         traffic_summarize(sys.argv[2], sys.argv[3], sys.argv[4])
         return
+    if len(sys.argv) >= 2 and sys.argv[1] == "--valu-summarize":
+        valu_summarize(sys.argv[2], sys.argv[3])
+        return
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -657,10 +717,11 @@ def main():
         kernels[name] = {"kernel": KERNEL_NAMES[name], "ms_per_launch": round(ms, 5),
                          "launches": int(k["launches"]), "gather_bytes": k["gather_bytes"],
                          "gather_GBps": round(k["gather_bytes"] / (ms * 1e-3) / 1e9, 1) if ms > 0 else None}
-    # Roofline under the gather model.  The dominant kernel is the one with the most time per
-    # step over all its launch groups (the long-segment groups included); its achieved rate is
-    # its algorithmic bytes per launch over its average launch duration.  Every launch group's
-    # fraction and the whole step's (all bytes of a step over ms_per_step) are reported beside it.
+    # Roofline under the gather model.  The dominant kernel is the one with the most algorithmic
+    # bytes per step over all its launch groups (the long-segment groups included); its achieved
+    # rate is its algorithmic bytes per launch over its average launch duration.  Every launch
+    # group's fraction and the whole step's (all bytes of a step over ms_per_step) are reported
+    # beside it.
     per_kernel = collections.defaultdict(lambda: {"bytes": 0.0, "ms": 0.0, "launches": 0, "groups": []})
     for g, k in kernels.items():
         pk = per_kernel[k["kernel"]]
@@ -668,7 +729,7 @@ def main():
         pk["ms"] += k["ms_per_launch"] * k["launches"]
         pk["launches"] += k["launches"]
         pk["groups"].append(g)
-    dname = max(per_kernel, key=lambda n: per_kernel[n]["ms"])
+    dname = max(per_kernel, key=lambda n: per_kernel[n]["bytes"])
     dk = per_kernel[dname]
     achieved = dk["bytes"] / (dk["ms"] * 1e-3) / 1e9
     tr = [traffic_for(g) for g in dk["groups"]]

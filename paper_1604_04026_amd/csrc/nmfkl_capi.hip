@@ -100,10 +100,6 @@ struct nmfkl_handle {
     double* d_chunk_obj = nullptr;  // per-chunk objective partial sums
     hipStream_t copy_stream = nullptr;
     hipEvent_t ev_copied[2] = {nullptr, nullptr}, ev_used[2] = {nullptr, nullptr};
-    // a second stream on which a half's binned launch runs beside its long-segment launches
-    // (in-HBM handles): forked from and joined back into the caller's stream with events
-    hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool used_recorded[2] = {false, false};
     int64_t staged_bytes = 0;       // H2D bytes of V moved (timing/measurement)
     SweepArgs* argtab = nullptr;       // device: kNumArgs sweep-argument entries
@@ -168,20 +164,19 @@ hipError_t take_event(nmfkl_handle* h, hipEvent_t* ev) {
     return hipEventCreate(ev);
 }
 
-// Starts a timed launch group on stream `on` (the handle's stream by default); returns the
-// index of the pending record or -1 when off.
-int timer_begin(nmfkl_handle* h, int kind, hipStream_t on = nullptr, bool use_on = false) {
+// Starts a timed launch group; returns the index of the pending record or -1 when off.
+int timer_begin(nmfkl_handle* h, int kind) {
     if (!h->prm.collect_timings) return -1;
     nmfkl_handle::Pending p{kind, nullptr, nullptr, false};
     if (take_event(h, &p.a) != hipSuccess || take_event(h, &p.b) != hipSuccess) return -1;
-    if (hipEventRecord(p.a, use_on ? on : h->stream) != hipSuccess) return -1;
+    if (hipEventRecord(p.a, h->stream) != hipSuccess) return -1;
     h->pending.push_back(p);
     return (int)h->pending.size() - 1;
 }
 
-void timer_end(nmfkl_handle* h, int idx, hipStream_t on = nullptr, bool use_on = false) {
+void timer_end(nmfkl_handle* h, int idx) {
     if (idx < 0) return;
-    (void)hipEventRecord(h->pending[idx].b, use_on ? on : h->stream);
+    (void)hipEventRecord(h->pending[idx].b, h->stream);
 }
 
 // Ends timed group prev (if any) and starts one of `kind` with the same event, for groups
@@ -239,9 +234,6 @@ void release(nmfkl_handle* h) {
     f(h->ooc_args); f(h->d_chunk_obj);
     if (h->h_lptr) (void)hipHostFree(h->h_lptr);
     if (h->copy_stream) (void)hipStreamDestroy(h->copy_stream);
-    if (h->side) (void)hipStreamDestroy(h->side);
-    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
-    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
 }
 
 // Variant for a segment of length L in the fused launch (-1: too long).  bin_shift > 0 maps
@@ -550,34 +542,9 @@ int refresh_model(nmfkl_handle* h) {
 // stats: some entry of tab collects statistics.
 hipError_t enqueue_plan(const BinPlan& plan, const SweepArgs* tab, unsigned long long* coop_words,
                         unsigned* dev_err, bool cooperative, bool lookahead, bool stats, hipStream_t s,
-                        nmfkl_handle* timed, int long_kind, int fused_kind, int open_timer = -1,
-                        nmfkl_handle* fork = nullptr) {
+                        nmfkl_handle* timed, int long_kind, int fused_kind, int open_timer = -1) {
     hipError_t e;
     const bool any_long = plan.single_blocks > 0 || !plan.rounds.empty();
-    if (fork && fork->side && any_long && plan.nblocks > 0) {
-        // The segments of the binned launch and of the long-segment launches are independent
-        // subproblems (eq. 3): the binned launch runs on the side stream beside the long ones,
-        // whose blocks fill the whole device at first and leave it block by block at the end.
-        // The long launches start first, so the cooperative launch finds the device free.
-        if ((e = hipEventRecord(fork->ev_fork, s)) != hipSuccess) return e;
-        int prev = open_timer;
-        const int tl = timed ? timer_switch(timed, prev, long_kind) : -1;
-        if (tl >= 0) prev = tl;
-        if ((e = launch_sweep_long_single(tab, plan.long_work, plan.single_blocks, s)) != hipSuccess) return e;
-        for (const auto& rd : plan.rounds)
-            if ((e = launch_sweep_long(tab, plan.long_work + rd.first, rd.nblocks, rd.grid, coop_words, rd.ngroups,
-                                       dev_err, rd.pmax, cooperative, s)) != hipSuccess)
-                return e;
-        if (timed) timer_end(timed, prev);
-        if ((e = hipStreamWaitEvent(fork->side, fork->ev_fork, 0)) != hipSuccess) return e;
-        const int tf = timed ? timer_begin(timed, fused_kind, fork->side, true) : -1;
-        if ((e = launch_sweep_fused(tab, plan.work, plan.segs, plan.nblocks, lookahead, stats, fork->side)) !=
-            hipSuccess)
-            return e;
-        if (timed) timer_end(timed, tf, fork->side, true);
-        if ((e = hipEventRecord(fork->ev_join, fork->side)) != hipSuccess) return e;
-        return hipStreamWaitEvent(s, fork->ev_join, 0);
-    }
     // timed groups follow each other: each one's start event ends the group before it
     // (open_timer: a group the caller started just before)
     int prev = open_timer;
@@ -673,16 +640,9 @@ int half_sweep(nmfkl_handle* h, int32_t t, bool fhalf) {
     int ai;
     if (fhalf) ai = (h->model == kModelCsc || h->model == kModelCscFresh) ? kArgFfromCsc : kArgFfromCsr;
     else ai = h->model == kModelCsr ? kArgWfromCsr : kArgWfromCsc;
-    if (!h->side && (plan.single_blocks > 0 || !plan.rounds.empty()) && plan.nblocks > 0) {
-        // created at the first half-sweep that has both kinds of launches (not for the handles
-        // a batch holds, whose launches are captured on the batch's own stream)
-        HIP_TRY(h, hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
-        HIP_TRY(h, hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
-        HIP_TRY(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
-    }
     HIP_TRY(h, enqueue_plan(plan, h->argtab + ai, h->coop_words, h->dev_err, true,
                             (h->prm.tuning & 1) != 0, h->prm.collect_stats != 0, h->stream, h,
-                            fhalf ? NMFKL_T_LONG_F : NMFKL_T_LONG_W, fhalf ? NMFKL_T_FUSED_F : NMFKL_T_FUSED_W, ts, h));
+                            fhalf ? NMFKL_T_LONG_F : NMFKL_T_LONG_W, fhalf ? NMFKL_T_FUSED_F : NMFKL_T_FUSED_W, ts));
     h->model = h->prm.tile_bf16 ? kModelNone : (fhalf ? kModelCsc : kModelCsr);
     return NMFKL_OK;
 }

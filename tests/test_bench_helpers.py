@@ -12,7 +12,7 @@ FIELDS = ["Correlation_Id", "Dispatch_Id", "Agent_Id", "Queue_Id", "Process_Id",
           "Accum_VGPR_Count", "SGPR_Count", "Counter_Name", "Counter_Value", "Start_Timestamp", "End_Timestamp"]
 
 
-def _write(path, counter, copy_kib, fused_kib, terms_kib):
+def _write(path, counter, copy_kib, fused_kib, terms_kib, long_kib=(30.0, 20.0, 50.0)):
     os.makedirs(path, exist_ok=True)
     rows, d = [], 0
 
@@ -23,9 +23,16 @@ def _write(path, counter, copy_kib, fused_kib, terms_kib):
                      "Counter_Value": v})
     for _ in range(3):
         add("__amd_rocclr_copyBuffer", copy_kib)
-    for sweep in range(4):               # F-half and W-half binned launches, then the terms
+    for sweep in range(4):               # each half: sums, long-segment launches, binned launch; then the terms
+        add("nmfkl::k_permute_jobs(...)", 7.0)
+        add("void nmfkl::k_sweep_long_single<8>(...)", long_kib[0])
         add("void nmfkl::k_sweep_fused<false>(...)", fused_kib[0])
+        add("nmfkl::k_permute_jobs(...)", 7.0)
+        add("void nmfkl::k_sweep_long_single<8>(...)", long_kib[1])
+        add("nmfkl::k_zero_u64(...)", 1.0)
+        add("void nmfkl::k_sweep_long_queue<20>(...)", long_kib[2])
         add("void nmfkl::k_sweep_fused<false>(...)", fused_kib[1])
+        add("nmfkl::k_permute_jobs(...)", 7.0)
         add("nmfkl::k_model_terms(...)", terms_kib)
     with open(os.path.join(path, "run_counter_collection.csv"), "w", newline="") as fh:
         w = csv.DictWriter(fh, fieldnames=FIELDS)
@@ -47,4 +54,37 @@ def test_traffic_summary_scales_by_the_copy(tmp_path):
     assert g["fused_W"]["fetch_bytes_per_launch"] == pytest.approx(1000.0 * 1024)
     assert g["fused_F"]["hbm_bytes_per_launch"] == pytest.approx((2000.0 + 80.0) * 1024)
     assert g["terms"]["fetch_bytes_per_launch"] == pytest.approx(200.0 * 1024)
+    assert g["long_F"]["fetch_bytes_per_launch"] == pytest.approx(60.0 * 1024)
+    assert g["long_W"]["fetch_bytes_per_launch"] == pytest.approx(140.0 * 1024)
     assert t["kernel_source_sha256_16"] == bench.source_hash()
+
+
+def test_valu_summary_weights_dispatches_by_duration(tmp_path):
+    path = tmp_path / "v"
+    os.makedirs(path)
+    rows, d = [], 0
+
+    def add(name, busy, util, dur):
+        nonlocal d
+        d += 1
+        for counter, v in (("VALUBusy", busy), ("VALUUtilization", util)):
+            rows.append({**{f: 0 for f in FIELDS}, "Dispatch_Id": d, "Kernel_Name": name, "Counter_Name": counter,
+                         "Counter_Value": v, "Start_Timestamp": 1000 * d, "End_Timestamp": 1000 * d + dur})
+    for sweep in range(3):
+        add("void nmfkl::k_sweep_long_single<8>(...)", 40.0, 90.0, 100)
+        add("void nmfkl::k_sweep_fused<false>(...)", 70.0, 85.0, 1000)
+        add("void nmfkl::k_sweep_long_single<8>(...)", 50.0, 90.0, 100)
+        add("void nmfkl::k_sweep_long_queue<20>(...)", 30.0, 90.0, 300)
+        add("void nmfkl::k_sweep_fused<false>(...)", 80.0, 80.0, 500)
+        add("nmfkl::k_model_terms(...)", 60.0, 99.0, 50)
+    with open(path / "run_counter_collection.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=FIELDS)
+        w.writeheader()
+        w.writerows(rows)
+    out = tmp_path / "valu.json"
+    bench.valu_summarize(str(path), str(out))
+    v = json.loads(out.read_text())
+    assert v["groups"]["fused_F"] == pytest.approx(70.0)
+    assert v["groups"]["long_W"] == pytest.approx((50.0 * 100 + 30.0 * 300) / 400, abs=0.05)
+    assert v["utilization"]["fused_W"] == pytest.approx(80.0)
+    assert v["kernel_source_sha256_16"] == bench.source_hash()
