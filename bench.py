@@ -580,8 +580,8 @@ def ablation_run(args, log):
         st = P.nmfkl_get_stats(h)
         W, F = dev.W.cpu().numpy(), dev.F.cpu().numpy()
         P.nmfkl_destroy(h)
-        rec = {"setting": name, "params": kw, "objective": D, "zeros_W": float(np.mean(W == 0)),
-               "zeros_F": float(np.mean(F == 0)), "monotone": all(D[i + 1] <= D[i] for i in range(9)),
+        rec = {"setting": name, "params": kw, "objective": D, "zeros_W": st["zeros_W"] / W.size,
+               "zeros_F": st["zeros_F"] / F.size, "monotone": all(D[i + 1] <= D[i] for i in range(9)),
                "stats": st}
         log(f"[ablation] {name}: D10 {D[-1]:.6g} zeros W {rec['zeros_W']:.3f} F {rec['zeros_F']:.3f}")
         out["runs"].append(rec)

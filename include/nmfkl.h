@@ -127,6 +127,9 @@ typedef struct nmfkl_stats {
     int64_t halvings;  /* descent-guard halvings */
     int64_t rejects;   /* steps abandoned by the guard */
     int64_t tmax_hits; /* coordinates stopped by t_max */
+    int64_t zeros_W;   /* exact zeros in W at the call (n x r entries), the sparsity of the
+                          paper's Table 2; -1 from nmfkl_model_get_stats */
+    int64_t zeros_F;   /* exact zeros in F at the call (m x r entries); -1 from nmfkl_model_get_stats */
 } nmfkl_stats;
 
 /* Launch groups timed when params.collect_timings is set. */
@@ -215,8 +218,8 @@ int nmfkl_objective_read(nmfkl_handle* h, double* D_out);
  * the handle carries between halves are recomputed before the next half-sweep. */
 int nmfkl_invalidate_model(nmfkl_handle* h);
 
-/* Counters accumulated since creation (all zero unless params.collect_stats).
- * Synchronises. */
+/* Counters accumulated since creation (all zero unless params.collect_stats), and the exact
+ * zeros of W and F at the call (always).  Synchronises. */
 int nmfkl_get_stats(nmfkl_handle* h, nmfkl_stats* out);
 
 /* Accumulated event times since creation or the last reset (all zero unless

@@ -78,7 +78,7 @@ class NmfklProblem(ctypes.Structure):
 
 class NmfklStats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in
-                ("coords", "evals", "steps", "halvings", "rejects", "tmax_hits")]
+                ("coords", "evals", "steps", "halvings", "rejects", "tmax_hits", "zeros_W", "zeros_F")]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

@@ -818,8 +818,8 @@ int create_ooc(const nmfkl_problem& pr, const nmfkl_params& prm, void* hip_strea
     h->obj_blocks = 4096;
     OOC_HIP(dalloc(&h->obj_partials, h->obj_blocks));
     OOC_HIP(alloc_results(h));
-    OOC_HIP(dalloc(&h->stats, 6));
-    OOC_HIP(hipMemsetAsync(h->stats, 0, 6 * sizeof(unsigned long long), h->stream));
+    OOC_HIP(dalloc(&h->stats, 8));
+    OOC_HIP(hipMemsetAsync(h->stats, 0, 8 * sizeof(unsigned long long), h->stream));
     OOC_HIP(hipMemsetAsync(h->dev_err, 0, sizeof(unsigned), h->stream));
     int ncu = 0;
     OOC_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
@@ -993,8 +993,8 @@ int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_str
     h->obj_blocks = (int)std::min<int64_t>(4096, std::max<int64_t>(1, pr.m / 8));
     CREATE_HIP(dalloc(&h->obj_partials, h->obj_blocks));
     CREATE_HIP(alloc_results(h));
-    CREATE_HIP(dalloc(&h->stats, 6));
-    CREATE_HIP(hipMemsetAsync(h->stats, 0, 6 * sizeof(unsigned long long), h->stream));
+    CREATE_HIP(dalloc(&h->stats, 8));
+    CREATE_HIP(hipMemsetAsync(h->stats, 0, 8 * sizeof(unsigned long long), h->stream));
     {
         int ncu = 0;
         CREATE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
@@ -1172,7 +1172,12 @@ int objective_finish(nmfkl_handle* h, double* D_out) {
 int nmfkl_get_stats(nmfkl_handle* h, nmfkl_stats* out) {
     if (!h) return fail(nullptr, NMFKL_E_INVAL, "null handle");
     if (!out) return fail(h, NMFKL_E_INVAL, "out is null");
-    unsigned long long c[6];
+    // exact zeros of W and F now, counted into words 6 and 7 of the statistics buffer
+    const nmfkl_problem& pr = h->prob;
+    HIP_TRY(h, hipMemsetAsync(h->stats + 6, 0, 2 * sizeof(unsigned long long), h->stream));
+    HIP_TRY(h, launch_count_zeros(pr.W, (int64_t)pr.n * pr.r, h->stats + 6, h->stream));
+    HIP_TRY(h, launch_count_zeros(pr.F, (int64_t)pr.m * pr.r, h->stats + 7, h->stream));
+    unsigned long long c[8];
     HIP_TRY(h, hipMemcpyAsync(c, h->stats, sizeof(c), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     out->coords = (int64_t)c[0];
@@ -1181,6 +1186,8 @@ int nmfkl_get_stats(nmfkl_handle* h, nmfkl_stats* out) {
     out->halvings = (int64_t)c[3];
     out->rejects = (int64_t)c[4];
     out->tmax_hits = (int64_t)c[5];
+    out->zeros_W = (int64_t)c[6];
+    out->zeros_F = (int64_t)c[7];
     return NMFKL_OK;
 }
 

@@ -477,6 +477,8 @@ int nmfkl_model_get_stats(nmfkl_model* m, nmfkl_stats* out) {
     out->halvings = (int64_t)c[3];
     out->rejects = (int64_t)c[4];
     out->tmax_hits = (int64_t)c[5];
+    out->zeros_W = -1;   // a model holds no factors being fitted
+    out->zeros_F = -1;
     return NMFKL_OK;
 }
 

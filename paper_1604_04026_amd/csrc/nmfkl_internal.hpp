@@ -238,6 +238,8 @@ hipError_t launch_build_maps(const int64_t* csr_ptr, const int32_t* csr_idx, con
 hipError_t launch_foldin(const FoldinArgs& f, const SweepArgs& a, int variant, const int32_t* docs,
                          int ndocs, hipStream_t stream);
 hipError_t launch_row_sums(const float* W, int64_t n, int r, double* out, hipStream_t stream);
+// *out += the number of exact zeros among A[0..count).
+hipError_t launch_count_zeros(const float* A, int64_t count, unsigned long long* out, hipStream_t stream);
 
 // Validation flag bits.
 enum : unsigned {

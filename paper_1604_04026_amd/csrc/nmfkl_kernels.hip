@@ -1303,6 +1303,24 @@ __global__ void k_row_sums(const float* __restrict__ W, int64_t n, int r, double
     out[i] = acc;
 }
 
+// Exact zeros of a factor (the sparsity the paper reports for its solutions, Table 2): each
+// block counts its grid-stride share in a register, then one atomic add per wave.
+__global__ void __launch_bounds__(256) k_count_zeros(const float* __restrict__ A, int64_t count,
+                                                    unsigned long long* __restrict__ out) {
+    unsigned long long c = 0;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += (int64_t)gridDim.x * blockDim.x)
+        c += A[q] == 0.0f ? 1ull : 0ull;
+    for (int m = 32; m >= 1; m >>= 1) c += __shfl_xor(c, m);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+}
+
+hipError_t launch_count_zeros(const float* A, int64_t count, unsigned long long* out, hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>(2048, (count + 255) / 256);
+    hipLaunchKernelGGL(k_count_zeros, dim3((unsigned)blocks), dim3(256), 0, stream, A, count, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_row_sums(const float* W, int64_t n, int r, double* out, hipStream_t stream) {
     hipLaunchKernelGGL(k_row_sums, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, W, n, r, out);
     return hipGetLastError();
