@@ -296,8 +296,30 @@ __device__ __forceinline__ double shfl_xor_f64(double v, int m) {
     return *reinterpret_cast<double*>(&p);
 }
 
+// Values that every lane of a segment holds bit for bit (the reduced sums, x_k, the column
+// sum) are wave-uniform when a wave holds lanes of one segment only (G >= 64): moved into
+// scalar registers with readfirstlane, the Newton logic's branches on them are uniform
+// branches instead of exec-mask sequences.
+template <bool UNI>
+__device__ __forceinline__ float seg_uniform(float v) {
+    if constexpr (UNI) return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+    else return v;
+}
+template <bool UNI>
+__device__ __forceinline__ double seg_uniform(double v) {
+    if constexpr (UNI) {
+        const long long b = __double_as_longlong(v);
+        const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xFFFFFFFFll));
+        const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+        return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    } else {
+        return v;
+    }
+}
+
 template <int G>
 struct WaveReducer {
+    static constexpr bool kUniform = G == 64;
     // float64 all-reduce over the segment's lanes (butterfly: identical on every lane)
     __device__ __forceinline__ double sum_f64(double v) {
 #pragma unroll
@@ -319,6 +341,7 @@ constexpr int kMaxRed = kCoopValues;
 
 template <int NT>
 struct BlockReducer {
+    static constexpr bool kUniform = true;
     float* red;
     int parity;
     double* red64;  // LDS, 2 * NT/64 doubles (float64 sums; optional)
@@ -380,6 +403,7 @@ constexpr unsigned kSpinLimit = 1u << 20;
 
 template <int NT>
 struct CoopReducer {
+    static constexpr bool kUniform = true;
     static constexpr int J = NT / kMaxRed;   // block groups per value
     static constexpr int kInFlight = 4;
     BlockReducer<NT> blk;
@@ -540,8 +564,11 @@ template <int E, int NACC, int OFF, class Later, class Commit, class Red, class 
 __device__ __forceinline__ void newton_coordinate(const SweepArgs& a, int s, const float (&tk)[E], float S1,
                                                   float S2, Later&& later, Commit&& commit, St& st, float* xs,
                                                   Red& red, Cnt& cnt) {
-    float xk = xs[s];
-    const double sA = a.sumA[s];
+    constexpr bool UNI = Red::kUniform;
+    float xk = seg_uniform<UNI>(xs[s]);
+    const double sA = seg_uniform<UNI>(a.sumA[s]);
+    S1 = seg_uniform<UNI>(S1);
+    S2 = seg_uniform<UNI>(S2);
     double P = sA + (double)a.alpha * xk + (double)a.beta;
     double g = P - (double)S1;
     float h = S2 + a.alpha;
@@ -597,8 +624,8 @@ __device__ __forceinline__ void newton_coordinate(const SweepArgs& a, int s, con
             red.sum(acc, OFF);
             cnt.add(1);
             Pn = sA + (double)a.alpha * xt + (double)a.beta;
-            gn = Pn - (double)acc[OFF];
-            hn = acc[OFF + 1] + a.alpha;
+            gn = Pn - (double)seg_uniform<UNI>(acc[OFF]);
+            hn = seg_uniform<UNI>(acc[OFF + 1]) + a.alpha;
             if (!(a.guard && d < 0.0f && g + gn < 0.0)) break;
             if (j == a.j_max) { rejected = true; break; }
             d *= 0.5f;
