@@ -80,10 +80,13 @@ typedef struct nmfkl_params {
     int32_t tuning;            /* implementation choices that do not change results; bit 0: batched
                                   (lookahead) derivative sums also for segments of 257..1024 nonzeros;
                                   bit 1 (batches): blocks ordered problem by problem rather than by
-                                  segment length across problems */
+                                  segment length across problems; bit 2: only the lane groups of 4 and
+                                  8 nonzeros per lane (power-of-two bin capacities), not those of 3
+                                  and 6 between them */
     int32_t bin_shift;         /* mapping of segments of <= 1024 nonzeros to lanes (0..3, default 0):
                                   a segment of L nonzeros runs on the smallest lane group that holds
-                                  L << bin_shift nonzeros (8, 16, 32, 64 or 256 lanes x 4).  Changes
+                                  L << bin_shift nonzeros (8 x 4, 16 x 4, 32 x 3 or 4, 64 x 3, 4, 6 or
+                                  8, 256 x 3 or 4).  Changes
                                   the summation order of eq. 6's sums, hence results in the last
                                   bits; results are identical for identical bin_shift */
     int32_t tile_bf16;         /* 0 (default): the fixed factor of a half-sweep is read in float32;
@@ -276,7 +279,7 @@ int nmfkl_batch_run(nmfkl_batch* b, int32_t t0, int32_t nsweeps);
 int nmfkl_batch_objective(nmfkl_batch* b, double* D_out);
 
 /* Autotuner: times one outer iteration (iteration t) under each candidate mapping
- * (bin_shift 0..2, tuning bits 0 and 1 off/on) on the batch, restoring W, F and the model values after
+ * (bin_shift 0..2, tuning bits 0, 1 and 2 off/on) on the batch, restoring W, F and the model values after
  * every trial, and keeps the fastest.  The factors are unchanged on return.  chosen (host,
  * may be NULL) receives the parameters now in use, with which nmfkl_create reproduces the
  * batch's results.  Synchronises. */

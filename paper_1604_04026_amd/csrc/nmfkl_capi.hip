@@ -239,11 +239,16 @@ void release(nmfkl_handle* h) {
 // Variant for a segment of length L in the fused launch (-1: too long).  bin_shift > 0 maps
 // a segment to the smallest variant holding L << bin_shift nonzeros (more lanes per nonzero;
 // the largest variant at most).
-int variant_for(int64_t L, int bin_shift) {
+// pow2_only (tuning bit 2): only the variants of 4 and 8 nonzeros per lane, i.e. power-of-two
+// capacities (a segment that fits E = 3 or 6 gets the next variant of the same lane count,
+// whose extra elements stay empty: the same sums in the same order).
+int variant_for(int64_t L, int bin_shift, bool pow2_only = false) {
     if (L > kMaxFusedLength) return -1;
     const int64_t Ls = L << bin_shift;
-    for (int v = 0; v < kNumVariants; ++v)
+    for (int v = 0; v < kNumVariants; ++v) {
+        if (pow2_only && (kVariants[v].E & (kVariants[v].E - 1)) != 0) continue;
         if (Ls <= (int64_t)kVariants[v].G * kVariants[v].E) return v;
+    }
     return kNumVariants - 1;
 }
 
@@ -269,7 +274,7 @@ void free_plan(BinPlan* p) {
 constexpr int kQueueMaxB = 20;
 
 int plan_bins(const std::vector<SegSource>& src, int long_capacity, int single_capacity, int bin_shift,
-              bool problem_major, BinPlan* plan, std::string* err) {
+              bool problem_major, BinPlan* plan, std::string* err, bool pow2_only = false) {
     struct LongSeg { int32_t q, prob; int64_t len; };
     const size_t ns = src.size();
     std::vector<std::vector<std::vector<int32_t>>> groups(kNumVariants, std::vector<std::vector<int32_t>>(ns));
@@ -281,7 +286,7 @@ int plan_bins(const std::vector<SegSource>& src, int long_capacity, int single_c
         for (int64_t q = 0; q < Q; ++q) {
             const int64_t L = ptr[q + 1] - ptr[q];
             const double bytes = (double)L * (8.0 + 4.0 * r) + 8.0 + 8.0 * r;
-            const int v = variant_for(L, bin_shift);
+            const int v = variant_for(L, bin_shift, pow2_only);
             if (v < 0) {
                 longs.push_back(LongSeg{(int32_t)q, src[i].prob, L});
                 plan->long_bytes += bytes;
@@ -841,7 +846,7 @@ int create_ooc(const nmfkl_problem& pr, const nmfkl_params& prm, void* hip_strea
             std::vector<int64_t> local(lptr.begin() + c.lptr, lptr.begin() + c.lptr + (c.seg1 - c.seg0) + 1);
             std::string why_plan;
             const int rc = plan_bins({SegSource{&local, pr.r, 0}}, h->long_capacity, h->single_capacity, prm.bin_shift, false, &c.plan,
-                                     &why_plan);
+                                     &why_plan, (prm.tuning & 4) != 0);
             if (rc) {
                 fail(h, rc, why_plan);
                 return bail(rc);
@@ -1010,10 +1015,10 @@ int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_str
         CREATE_HIP(hipMemcpy(h->hptr_csr.data(), pr.csr_ptr, h->hptr_csr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
         std::string why_plan;
         int rc = plan_bins({SegSource{&h->hptr_csc, pr.r, 0}}, h->long_capacity, h->single_capacity, prm.bin_shift, false, &h->binF,
-                           &why_plan);
+                           &why_plan, (prm.tuning & 4) != 0);
         if (!rc)
             rc = plan_bins({SegSource{&h->hptr_csr, pr.r, 0}}, h->long_capacity, h->single_capacity, prm.bin_shift, false, &h->binW,
-                           &why_plan);
+                           &why_plan, (prm.tuning & 4) != 0);
         if (rc) {
             fail(h, rc, why_plan);
             return bail(rc);
@@ -1289,8 +1294,9 @@ int batch_plan(nmfkl_batch* b) {
     }
     std::string why;
     const bool pm = (b->prm.tuning & 2) != 0;
-    int rc = plan_bins(srcF, b->long_capacity, b->single_capacity, b->prm.bin_shift, pm, &b->plan[0], &why);
-    if (!rc) rc = plan_bins(srcW, b->long_capacity, b->single_capacity, b->prm.bin_shift, pm, &b->plan[1], &why);
+    const bool p2 = (b->prm.tuning & 4) != 0;
+    int rc = plan_bins(srcF, b->long_capacity, b->single_capacity, b->prm.bin_shift, pm, &b->plan[0], &why, p2);
+    if (!rc) rc = plan_bins(srcW, b->long_capacity, b->single_capacity, b->prm.bin_shift, pm, &b->plan[1], &why, p2);
     if (rc) return bfail(b, rc, why);
     const int groups = std::max(std::max(b->plan[0].max_groups, b->plan[1].max_groups), 1);
     const int pmax = std::max(std::max(b->plan[0].max_pmax, b->plan[1].max_pmax), 1);
@@ -1537,9 +1543,9 @@ int nmfkl_batch_tune(nmfkl_batch* b, int32_t t, nmfkl_params* chosen) {
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e == hipSuccess) e = copy_all(true);
     for (int shift = 0; shift <= 2 && e == hipSuccess && rc == NMFKL_OK; ++shift)
-        for (int bits = 0; bits <= 3 && e == hipSuccess && rc == NMFKL_OK; ++bits) {
+        for (int bits = 0; bits <= 7 && e == hipSuccess && rc == NMFKL_OK; ++bits) {
             b->prm.bin_shift = shift;
-            b->prm.tuning = (orig.tuning & ~3) | bits;
+            b->prm.tuning = (orig.tuning & ~7) | bits;
             rc = batch_plan(b);
             if (rc) break;
             float ms = 0.0f;

@@ -208,6 +208,23 @@ def test_stats_counters():
     assert 0 < out[1][2]["zeros_F"] < F.size
 
 
+def test_power_of_two_bins_give_identical_results():
+    """tuning bit 2 maps segments that fit 3 or 6 nonzeros per lane to the 4- or 8-per-lane
+    group of the same lane count: the extra elements stay empty, so both halves' factors are
+    bit for bit those of the default bins."""
+    prob = CASES["corpus_mid"]()
+    out = []
+    for tuning in (0, 4):
+        dev = P.upload(prob, "cuda")
+        h = P.nmfkl_create(dev, P.nmfkl_params_default(tuning=tuning))
+        for t in range(2):
+            P.nmfkl_sweep_F(h, t)
+            P.nmfkl_sweep_W(h, t)
+        out.append((dev.W.cpu().numpy(), dev.F.cpu().numpy()))
+        P.nmfkl_destroy(h)
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
 def long_corpus(seed=0):
     """Rows up to ~20k nonzeros: single-block (1025..4096) and multi-block long segments."""
     n, m, r = 2000, 20000, 12
