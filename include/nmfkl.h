@@ -362,10 +362,11 @@ int nmfkl_server_create(nmfkl_model* m, int64_t mem_budget_bytes, int32_t lanes,
                         int32_t max_queued, nmfkl_server** out);
 
 /* Submit one document (host arrays, copied before returning).  timeout_s > 0: if it has not
- * been launched timeout_s seconds after submission it is not launched and is returned with
- * status NMFKL_RESULT_EXPIRED (<= 0: no limit).  NMFKL_E_BUSY: max_queued documents are
- * waiting (retry later); NMFKL_E_NOMEM: the memory budget is full now (retry later);
- * NMFKL_E_INVAL: malformed; NMFKL_E_UNSUPPORTED: too long. */
+ * been launched timeout_s seconds after submission it is not launched and the first
+ * nmfkl_server_poll after that returns it with status NMFKL_RESULT_EXPIRED, also while every
+ * lane is busy (<= 0: no limit).  NMFKL_E_BUSY: max_queued documents are waiting (retry
+ * later); NMFKL_E_NOMEM: the memory budget is full now (retry later); NMFKL_E_INVAL:
+ * malformed; NMFKL_E_UNSUPPORTED: too long. */
 int nmfkl_server_submit(nmfkl_server* s, uint64_t req_id, int32_t L, const int32_t* word_idx,
                         const float* counts, double timeout_s);
 

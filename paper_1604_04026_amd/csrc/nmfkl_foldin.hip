@@ -171,6 +171,7 @@ struct nmfkl_server {
     };
     std::vector<Lane> lanes;
     std::deque<Req> pending;
+    int64_t timed_pending = 0;       // waiting documents that have a time limit
     int64_t words_in_flight = 0;     // pending + launched
     struct Done {
         uint64_t id;
@@ -206,6 +207,7 @@ void release_lane(nmfkl_server::Lane& L) {
 }
 
 void finish_unlaunched(nmfkl_server* s, nmfkl_server::Req&& q, int status, double t) {
+    if (q.expires > 0.0) --s->timed_pending;
     nmfkl_server::Done d;
     d.id = q.id;
     d.passes = 0;
@@ -265,6 +267,22 @@ int collect(nmfkl_server* s) {
     return NMFKL_OK;
 }
 
+// Return every waiting document whose time limit has passed (only while some have one), so
+// that a caller learns of it while the lanes are still busy.
+void expire_pending(nmfkl_server* s) {
+    if (s->timed_pending == 0) return;
+    const double t = now_seconds();
+    for (auto it = s->pending.begin(); it != s->pending.end();) {
+        if (it->expires > 0.0 && t > it->expires) {
+            nmfkl_server::Req q = std::move(*it);
+            it = s->pending.erase(it);
+            finish_unlaunched(s, std::move(q), NMFKL_RESULT_EXPIRED, t);
+        } else {
+            ++it;
+        }
+    }
+}
+
 // Form a batch for every idle lane from the waiting documents (FIFO; those past their time
 // limit are returned as expired instead) and launch it.
 int dispatch(nmfkl_server* s) {
@@ -285,6 +303,7 @@ int dispatch(nmfkl_server* s) {
                     continue;
                 }
             }
+            if (q.expires > 0.0) --s->timed_pending;
             std::memcpy(L.h_idx + w, q.idx.data(), (size_t)q.L * sizeof(int32_t));
             std::memcpy(L.h_val + w, q.val.data(), (size_t)q.L * sizeof(float));
             w += q.L;
@@ -573,6 +592,7 @@ int nmfkl_server_submit(nmfkl_server* s, uint64_t req_id, int32_t L, const int32
     q.expires = timeout_s > 0.0 ? q.t_submit + timeout_s : 0.0;
     q.idx.assign(word_idx, word_idx + L);
     q.val.assign(counts, counts + L);
+    if (q.expires > 0.0) ++s->timed_pending;
     s->pending.push_back(std::move(q));
     s->words_in_flight += L;
     return NMFKL_OK;
@@ -594,6 +614,7 @@ int nmfkl_server_poll(nmfkl_server* s, int32_t max_results, nmfkl_result* out, f
     if (!s || !n_out || (max_results > 0 && (!out || !f_out))) return sfail(s, NMFKL_E_INVAL, "null argument");
     int rc = collect(s);
     if (rc) return rc;
+    expire_pending(s);
     rc = dispatch(s);
     if (rc) return rc;
     const int r = s->model->r;

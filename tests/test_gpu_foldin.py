@@ -192,7 +192,7 @@ def test_server_returns_each_document_when_it_finishes(small_serving):
 
 def test_server_timeout_cancel_and_busy(small_serving):
     """With the single lane busy: a document whose time limit passes while it waits comes back
-    expired; a waiting document can be cancelled, a launched one cannot; the waiting queue
+    expired, before the lane frees; a waiting document can be cancelled, a launched one cannot; the waiting queue
     refuses documents beyond max_queued with NMFKL_E_BUSY."""
     import torch
     W = small_serving[0]
@@ -209,9 +209,12 @@ def test_server_timeout_cancel_and_busy(small_serving):
     assert P.nmfkl_server_cancel(srv, 2) == -1               # already withdrawn
     assert P.nmfkl_server_cancel(srv, 1000) == -1            # launched: runs to the end
     assert P.nmfkl_server_submit(srv, 4, *fast[3]) == 0      # a slot is free again
-    out, _ = _drain(srv, 5)
+    out, polls = _drain(srv, 5)
     assert out[1000][6] == 0 and out[3][6] == 0 and out[4][6] == 0
     assert out[1][6] == P.RESULT_EXPIRED and out[1][1] == 0
+    # the expired document is returned while the slow one still holds the lane
+    first = {i: min(k for k, p in enumerate(polls) if i in p) for i in (1, 1000)}
+    assert first[1] < first[1000], polls
     assert out[2][6] == P.RESULT_CANCELLED and out[2][1] == 0
     # the words of launched documents are released once their lane is free again
     t0 = time.time()
