@@ -662,7 +662,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sweep's sharding over "
-              "several GPUs is a design, not part of this build.", file=sys.stderr)
+              "several GPUs is described as a design only and is not implemented.", file=sys.stderr)
         sys.exit(2)
     if args.traffic_run:
         traffic_run(args)

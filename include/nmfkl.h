@@ -48,7 +48,7 @@ extern "C" {
 #define NMFKL_E_DEVICE (-3)      /* HIP runtime error or device-side failure */
 #define NMFKL_E_NONFINITE (-4)   /* a factor holds a NaN/Inf (detected at a synchronising call) */
 #define NMFKL_E_BUSY (-5)        /* no free slot (serving) */
-#define NMFKL_E_UNSUPPORTED (-6) /* valid request outside this build's limits */
+#define NMFKL_E_UNSUPPORTED (-6) /* valid request outside the library's limits */
 
 #define NMFKL_R_MAX 128          /* largest supported rank r */
 
