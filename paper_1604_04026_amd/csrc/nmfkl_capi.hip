@@ -28,7 +28,8 @@ struct BinPlan {
     // then one queue launch for the rest (blocks take parts through a ticket counter)
     LongWork* long_work = nullptr;  // device: single-block entries, then each launch's parts
     int single_blocks = 0;
-    struct Round { int first, nblocks, ngroups, pmax, grid; };  // nblocks: parts; grid: blocks
+    // nblocks: parts; grid: blocks; wide: one part per block of kWideThreads
+    struct Round { int first, nblocks, ngroups, pmax, grid; bool wide; };
     std::vector<Round> rounds;
     int max_groups = 0, max_pmax = 0;
     // algorithmic (gather-model) bytes and updates of the fused and of the long launches
@@ -80,6 +81,7 @@ struct nmfkl_handle {
     unsigned* dev_err = nullptr;       // device-side error flags (bounded waits), in dres's last word
     int long_capacity = 0;             // co-resident blocks of the cooperative long-segment kernel
     int single_capacity = 0;           // co-resident blocks of the single-block long-segment kernel
+    int wide_capacity = 0;             // co-resident blocks of its wide form
     BinPlan binF, binW;
     std::vector<int64_t> hptr_csc, hptr_csr;  // host copies of the segment pointers
     // out-of-core V (params.out_of_core): chunks of whole columns (F-half) / rows (W-half)
@@ -272,9 +274,14 @@ void free_plan(BinPlan* p) {
 // (B up to 387) the segments of more than 20 blocks run faster in packs (long_W 128 ms with
 // this bound, 131 ms with 32, 133 ms with everything queued; 12 costs the corpus 0.06 ms).
 constexpr int kQueueMaxB = 20;
+// A queue of more than this many waves of the co-resident capacity runs on the wide blocks:
+// on the corpus (3.5 waves) two blocks of 256 per unit are faster (long_W 1.32 ms against
+// 1.53 ms with wide blocks), on the large corpus (about 50 waves) the wide blocks are (long_W
+// 129 ms against 137 ms; wide blocks for the launches of the longest segments alone: 135 ms).
+constexpr int kWideQueueWaves = 8;
 
-int plan_bins(const std::vector<SegSource>& src, int long_capacity, int single_capacity, int bin_shift,
-              bool problem_major, BinPlan* plan, std::string* err, bool pow2_only = false) {
+int plan_bins(const std::vector<SegSource>& src, int long_capacity, int single_capacity, int wide_capacity,
+              int bin_shift, bool problem_major, BinPlan* plan, std::string* err, bool pow2_only = false) {
     struct LongSeg { int32_t q, prob; int64_t len; };
     const size_t ns = src.size();
     std::vector<std::vector<std::vector<int32_t>>> groups(kNumVariants, std::vector<std::vector<int32_t>>(ns));
@@ -369,12 +376,14 @@ int plan_bins(const std::vector<SegSource>& src, int long_capacity, int single_c
     plan->single_blocks = (int)lw.size();
     // Segments of more than kQueueMaxB blocks run in launches of their own, each holding the
     // next segments that fit (longest first): in the queue, the first blocks to take a part of
-    // such a segment would wait for many partners while the blocks ahead of them finish.  The
-    // rest share one queue launch.
-    auto add_launch = [&](const std::vector<LongSeg>& list, bool as_queue) {
-        BinPlan::Round cur{(int)lw.size(), 0, 0, 0, 0};
+    // such a segment would wait for many partners while the blocks ahead of them finish.
+    // These launches use the wide blocks (parts of kWideCapacity).  The rest share one queue
+    // launch.
+    auto wide_blocks_of = [](const LongSeg& l) { return (int)((l.len + kWideCapacity - 1) / kWideCapacity); };
+    auto add_launch = [&](const std::vector<LongSeg>& list, bool as_queue, bool wide) {
+        BinPlan::Round cur{(int)lw.size(), 0, 0, 0, 0, wide};
         for (const LongSeg& l : list) {
-            const int B = blocks_of(l);
+            const int B = wide ? wide_blocks_of(l) : blocks_of(l);
             // B = 1 parts exchange nothing: they share group 0
             const int group = B > 1 ? cur.ngroups++ : 0;
             for (int p = 0; p < B; ++p) lw.push_back(LongWork{l.q, p, B, group, l.prob, 0});
@@ -382,35 +391,42 @@ int plan_bins(const std::vector<SegSource>& src, int long_capacity, int single_c
             cur.pmax = std::max(cur.pmax, B);
         }
         cur.ngroups = std::max(cur.ngroups, 1);
-        cur.grid = as_queue ? std::min(cur.nblocks, long_capacity) : cur.nblocks;
+        cur.grid = as_queue ? std::min(cur.nblocks, wide ? wide_capacity : long_capacity) : cur.nblocks;
         plan->rounds.push_back(cur);
     };
     std::vector<LongSeg> pack, rest;
     int pack_blocks = 0;
     for (const LongSeg& l : queued) {
-        const int B = blocks_of(l);
-        if (B > long_capacity) {
-            *err = "a segment of " + std::to_string(l.len) + " nonzeros needs " + std::to_string(B) +
-                   " co-resident blocks; this device holds " + std::to_string(long_capacity);
+        const int B = blocks_of(l), Bw = wide_blocks_of(l);
+        if (B > kQueueMaxB && Bw > wide_capacity) {
+            *err = "a segment of " + std::to_string(l.len) + " nonzeros needs " + std::to_string(Bw) +
+                   " co-resident blocks; this device holds " + std::to_string(wide_capacity);
             return NMFKL_E_UNSUPPORTED;
         }
         if (B > kQueueMaxB) {
-            if (pack_blocks + B > long_capacity) {
-                add_launch(pack, false);
+            if (pack_blocks + Bw > wide_capacity) {
+                add_launch(pack, false, true);
                 pack.clear();
                 pack_blocks = 0;
             }
             pack.push_back(l);
-            pack_blocks += B;
-        } else if (!pack.empty() && pack_blocks + B <= long_capacity) {
+            pack_blocks += Bw;
+        } else if (!pack.empty() && pack_blocks + Bw <= wide_capacity) {
             pack.push_back(l);   // fills the last launch of large segments
-            pack_blocks += B;
+            pack_blocks += Bw;
         } else {
             rest.push_back(l);
         }
     }
-    if (!pack.empty()) add_launch(pack, false);
-    if (!rest.empty()) add_launch(rest, true);
+    if (!pack.empty()) add_launch(pack, false, true);
+    if (!rest.empty()) {
+        // a queue of many waves takes the wide blocks too (fewer partners per exchange, whose
+        // compute times spread when the chunk slices exceed the L2); a short one keeps two
+        // blocks per unit, whose exchanges overlap the other block's compute
+        int64_t parts = 0;
+        for (const LongSeg& l : rest) parts += blocks_of(l);
+        add_launch(rest, true, parts > (int64_t)kWideQueueWaves * long_capacity);
+    }
     for (const auto& r : plan->rounds) {
         plan->max_groups = std::max(plan->max_groups, r.ngroups);
         plan->max_pmax = std::max(plan->max_pmax, r.pmax);
@@ -558,7 +574,7 @@ hipError_t enqueue_plan(const BinPlan& plan, const SweepArgs* tab, unsigned long
     if ((e = launch_sweep_long_single(tab, plan.long_work, plan.single_blocks, s)) != hipSuccess) return e;
     for (const auto& rd : plan.rounds)
         if ((e = launch_sweep_long(tab, plan.long_work + rd.first, rd.nblocks, rd.grid, coop_words, rd.ngroups,
-                                   dev_err, rd.pmax, cooperative, s)) != hipSuccess)
+                                   dev_err, rd.pmax, cooperative, rd.wide, s)) != hipSuccess)
             return e;
     const int tf = (timed && plan.nblocks) ? timer_switch(timed, prev, fused_kind) : -1;
     if (tf >= 0) prev = tf;
@@ -830,7 +846,8 @@ int create_ooc(const nmfkl_problem& pr, const nmfkl_params& prm, void* hip_strea
     OOC_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
     h->long_capacity = long_kernel_blocks_per_cu() * ncu;
     h->single_capacity = long_single_blocks_per_cu() * ncu;
-    if (h->long_capacity <= 0) {
+    h->wide_capacity = wide_kernel_blocks_per_cu() * ncu;
+    if (h->long_capacity <= 0 || h->wide_capacity <= 0) {
         fail(h, NMFKL_E_DEVICE, "occupancy query of the long-segment kernel failed");
         return bail(NMFKL_E_DEVICE);
     }
@@ -845,7 +862,7 @@ int create_ooc(const nmfkl_problem& pr, const nmfkl_params& prm, void* hip_strea
         for (auto& c : h->chunks[half]) {
             std::vector<int64_t> local(lptr.begin() + c.lptr, lptr.begin() + c.lptr + (c.seg1 - c.seg0) + 1);
             std::string why_plan;
-            const int rc = plan_bins({SegSource{&local, pr.r, 0}}, h->long_capacity, h->single_capacity, prm.bin_shift, false, &c.plan,
+            const int rc = plan_bins({SegSource{&local, pr.r, 0}}, h->long_capacity, h->single_capacity, h->wide_capacity, prm.bin_shift, false, &c.plan,
                                      &why_plan, (prm.tuning & 4) != 0);
             if (rc) {
                 fail(h, rc, why_plan);
@@ -1005,7 +1022,8 @@ int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_str
         CREATE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
         h->long_capacity = long_kernel_blocks_per_cu() * ncu;
         h->single_capacity = long_single_blocks_per_cu() * ncu;
-        if (h->long_capacity <= 0) {
+        h->wide_capacity = wide_kernel_blocks_per_cu() * ncu;
+        if (h->long_capacity <= 0 || h->wide_capacity <= 0) {
             fail(h, NMFKL_E_DEVICE, "occupancy query of the long-segment kernel failed");
             return bail(NMFKL_E_DEVICE);
         }
@@ -1014,10 +1032,10 @@ int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_str
         CREATE_HIP(hipMemcpy(h->hptr_csc.data(), pr.csc_ptr, h->hptr_csc.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
         CREATE_HIP(hipMemcpy(h->hptr_csr.data(), pr.csr_ptr, h->hptr_csr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
         std::string why_plan;
-        int rc = plan_bins({SegSource{&h->hptr_csc, pr.r, 0}}, h->long_capacity, h->single_capacity, prm.bin_shift, false, &h->binF,
+        int rc = plan_bins({SegSource{&h->hptr_csc, pr.r, 0}}, h->long_capacity, h->single_capacity, h->wide_capacity, prm.bin_shift, false, &h->binF,
                            &why_plan, (prm.tuning & 4) != 0);
         if (!rc)
-            rc = plan_bins({SegSource{&h->hptr_csr, pr.r, 0}}, h->long_capacity, h->single_capacity, prm.bin_shift, false, &h->binW,
+            rc = plan_bins({SegSource{&h->hptr_csr, pr.r, 0}}, h->long_capacity, h->single_capacity, h->wide_capacity, prm.bin_shift, false, &h->binW,
                            &why_plan, (prm.tuning & 4) != 0);
         if (rc) {
             fail(h, rc, why_plan);
@@ -1241,6 +1259,7 @@ struct nmfkl_batch {
     int64_t* t_dev = nullptr;
     int long_capacity = 0;
     int single_capacity = 0;
+    int wide_capacity = 0;
     int graph_coop = -1;
     std::vector<std::pair<int, hipGraphExec_t>> graphs;
     std::string err;
@@ -1295,8 +1314,8 @@ int batch_plan(nmfkl_batch* b) {
     std::string why;
     const bool pm = (b->prm.tuning & 2) != 0;
     const bool p2 = (b->prm.tuning & 4) != 0;
-    int rc = plan_bins(srcF, b->long_capacity, b->single_capacity, b->prm.bin_shift, pm, &b->plan[0], &why, p2);
-    if (!rc) rc = plan_bins(srcW, b->long_capacity, b->single_capacity, b->prm.bin_shift, pm, &b->plan[1], &why, p2);
+    int rc = plan_bins(srcF, b->long_capacity, b->single_capacity, b->wide_capacity, b->prm.bin_shift, pm, &b->plan[0], &why, p2);
+    if (!rc) rc = plan_bins(srcW, b->long_capacity, b->single_capacity, b->wide_capacity, b->prm.bin_shift, pm, &b->plan[1], &why, p2);
     if (rc) return bfail(b, rc, why);
     const int groups = std::max(std::max(b->plan[0].max_groups, b->plan[1].max_groups), 1);
     const int pmax = std::max(std::max(b->plan[0].max_pmax, b->plan[1].max_pmax), 1);
@@ -1400,6 +1419,7 @@ int nmfkl_batch_create(int32_t nprob, const nmfkl_problem* probs, const nmfkl_pa
     }
     b->long_capacity = b->hs[0]->long_capacity;
     b->single_capacity = b->hs[0]->single_capacity;
+    b->wide_capacity = b->hs[0]->wide_capacity;
     std::vector<SweepArgs> args(2 * (size_t)nprob);
     std::vector<PermJob> jobs(2 * (size_t)nprob);
     for (int half = 0; half < 2; ++half) {

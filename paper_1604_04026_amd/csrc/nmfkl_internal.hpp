@@ -166,11 +166,19 @@ constexpr int kMaxFusedLength = 1024;   // 256 * 4
 constexpr int kLongThreads = 256;
 constexpr int kLongE = 8;
 constexpr int kLongCapacity = kLongThreads * kLongE;
-// Segments longer than kLongCapacity: blocks of kCoopE nonzeros per thread (two blocks per
-// compute unit; more nonzeros per unit than three blocks of kLongE), B = ceil(L /
-// kCoopCapacity) of them per segment.
+// Segments longer than kLongCapacity: blocks of kCoopThreads threads x kCoopE nonzeros
+// (kCoopBlocksPerCU blocks per compute unit; more nonzeros per unit than three blocks of
+// kLongE), B = ceil(L / kCoopCapacity) of them per segment.
+constexpr int kCoopThreads = 256;
+constexpr int kCoopBlocksPerCU = 2;
 constexpr int kCoopE = 20;
-constexpr int kCoopCapacity = kLongThreads * kCoopE;
+constexpr int kCoopCapacity = kCoopThreads * kCoopE;
+// The launches of the longest segments (more than kQueueMaxB blocks of kCoopCapacity) use
+// blocks twice as wide, one per compute unit: the same nonzeros per unit, half as many
+// partners in each cross-block exchange.
+constexpr int kWideThreads = 512;
+constexpr int kWideBlocksPerCU = 1;
+constexpr int kWideCapacity = kWideThreads * kCoopE;
 
 // A block of a long-segment launch.
 struct LongWork {
@@ -206,12 +214,15 @@ constexpr int kCoopValues = 2 * kChunk;
 // tagged partial words and the counter first (2 * pmax * kCoopValues words per group, pmax =
 // largest B in the list, then one counter word).  cooperative = false: ordinary launch of
 // the same grid (inside a captured graph), which relies on the grid fitting the device's
-// co-resident capacity; the waits stay bounded.
+// co-resident capacity; the waits stay bounded.  wide: one part per block of kWideThreads
+// (grid == nparts; the parts were cut at kWideCapacity).
 hipError_t launch_sweep_long(const SweepArgs* tab, const LongWork* work, int nparts, int grid,
                              unsigned long long* words, int ngroups, unsigned* err, int pmax, bool cooperative,
-                             hipStream_t stream);
+                             bool wide, hipStream_t stream);
 // Co-resident blocks of the cooperative long-segment kernel per compute unit (0 on failure).
 int long_kernel_blocks_per_cu();
+// ... and of its wide form.
+int wide_kernel_blocks_per_cu();
 // ... and of the single-block long-segment kernel (0 on failure).
 int long_single_blocks_per_cu();
 hipError_t launch_model_objective(const int64_t* csc_ptr, const int32_t* csc_idx,

@@ -946,35 +946,36 @@ hipError_t launch_sweep_fused(const SweepArgs* tab, const BlockWork* work, const
 // Long segments, lookahead form.  Segments of at most kLongCapacity nonzeros take one block
 // of kLongThreads threads x kLongE nonzeros (COOP = false, ordinary launch; 3 blocks per
 // compute unit within 168 registers).  Longer ones take B = ceil(L / kCoopCapacity) blocks of
-// kCoopE = 20 nonzeros per thread (COOP = true: 2 blocks per compute unit, 10240 nonzeros
-// per unit, more than 3 blocks of 2048) that cooperate through CoopReducer; all blocks of
+// kCoopThreads threads x kCoopE nonzeros (COOP = true: 256 x 20 at 2 blocks per compute unit,
+// 10240 nonzeros per unit, more than 3 blocks of 2048) that cooperate through CoopReducer; all blocks of
 // such a launch are co-resident (cooperative launch), so every wait ends.  Counts and ids
 // live in LDS, the model values in registers, w and u are recomputed from the model at each
 // chunk start, and tile chunks are 4 coordinates wide.
 constexpr int kLongCW = kChunkMajorW;
 constexpr int kCoopCW = kChunkMajorW;
 
-// One block's part of a long segment: the segment's x and column sums into LDS, the sweep,
-// and x back (part 0).  COOP: the blocks of the segment exchange through CoopReducer.
-template <bool COOP, int E>
+// One block's part of a long segment (NT threads): the segment's x and column sums into LDS,
+// the sweep, and x back (part 0).  COOP: the blocks of the segment exchange through
+// CoopReducer.
+template <bool COOP, int E, int NT>
 __device__ __forceinline__ void long_part(const SweepArgs* __restrict__ tab, const LongWork& wk,
                                           unsigned long long* words, unsigned* err, int pmax, float* xs,
                                           float* red_lds, double* tmp, double* bcast, int32_t* s_id, float* s_v,
                                           double* sA_lds) {
-    constexpr int CAP = kLongThreads * E;
+    constexpr int CAP = NT * E;
     SweepArgs a = tab[wk.prob];
     const int lane = threadIdx.x;
-    LdsElemsNoWU<E, kLongThreads> st;
+    LdsElemsNoWU<E, NT> st;
     st.idp = s_id + lane;
     st.vp = s_v + lane;
-    for (int s = lane; s < a.r; s += kLongThreads) {
+    for (int s = lane; s < a.r; s += NT) {
         xs[s] = a.X[(int64_t)wk.seg * a.r + a.ids[s]];
         sA_lds[s] = a.sumA[s];
     }
     a.sumA = sA_lds;
     __syncthreads();
     if constexpr (COOP) {
-        CoopReducer<kLongThreads> red;
+        CoopReducer<NT> red;
         red.blk.red = red_lds;
         red.blk.parity = 0;
         red.tmp = tmp;
@@ -984,15 +985,15 @@ __device__ __forceinline__ void long_part(const SweepArgs* __restrict__ tab, con
         red.B = wk.B;
         red.part = wk.part;
         red.round = 0;
-        sweep_segment<kLongThreads, false, true, kCoopCW>(a, wk.seg, true, lane, wk.part * CAP,
+        sweep_segment<NT, false, true, kCoopCW>(a, wk.seg, true, lane, wk.part * CAP,
                                                           wk.part == 0, xs, red, st);
     } else {
-        BlockReducer<kLongThreads> red{red_lds, 0, nullptr};
-        sweep_segment<kLongThreads, false, true, kLongCW>(a, wk.seg, true, lane, 0, true, xs, red, st);
+        BlockReducer<NT> red{red_lds, 0, nullptr};
+        sweep_segment<NT, false, true, kLongCW>(a, wk.seg, true, lane, 0, true, xs, red, st);
     }
     __syncthreads();
     if (wk.part == 0)
-        for (int s = lane; s < a.r; s += kLongThreads) a.X[(int64_t)wk.seg * a.r + a.ids[s]] = xs[s];
+        for (int s = lane; s < a.r; s += NT) a.X[(int64_t)wk.seg * a.r + a.ids[s]] = xs[s];
 }
 
 template <int E>
@@ -1003,23 +1004,24 @@ k_sweep_long_single(const SweepArgs* __restrict__ tab, const LongWork* __restric
     __shared__ int32_t s_id[kLongThreads * E];
     __shared__ float s_v[kLongThreads * E];
     __shared__ double sA_lds[NMFKL_R_MAX];
-    long_part<false, E>(tab, work[blockIdx.x], nullptr, nullptr, 0, xs, red_lds, nullptr, nullptr, s_id, s_v,
+    long_part<false, E, kLongThreads>(tab, work[blockIdx.x], nullptr, nullptr, 0, xs, red_lds, nullptr, nullptr, s_id, s_v,
                         sA_lds);
 }
 
-// Long segments whose parts all fit the co-resident capacity: one part per block.
-template <int E>
-__global__ void __launch_bounds__(kLongThreads, 2)
+// Long segments whose parts all fit the co-resident capacity: one part per block of NT
+// threads (kCoopThreads, or kWideThreads for the launches of the longest segments).
+template <int E, int NT, int BPC>
+__global__ void __launch_bounds__(NT, BPC)
 k_sweep_long_flat(const SweepArgs* __restrict__ tab, const LongWork* __restrict__ work,
                   unsigned long long* __restrict__ words, unsigned* __restrict__ err, int pmax) {
     __shared__ float xs[NMFKL_R_MAX];
-    __shared__ float red_lds[2 * (kLongThreads / 64) * kMaxRed];
-    __shared__ double tmp[CoopReducer<kLongThreads>::J * kMaxRed];
+    __shared__ float red_lds[2 * (NT / 64) * kMaxRed];
+    __shared__ double tmp[CoopReducer<NT>::J * kMaxRed];
     __shared__ double bcast[kMaxRed];
-    __shared__ int32_t s_id[kLongThreads * E];
-    __shared__ float s_v[kLongThreads * E];
+    __shared__ int32_t s_id[NT * E];
+    __shared__ float s_v[NT * E];
     __shared__ double sA_lds[NMFKL_R_MAX];
-    long_part<true, E>(tab, work[blockIdx.x], words, err, pmax, xs, red_lds, tmp, bcast, s_id, s_v, sA_lds);
+    long_part<true, E, NT>(tab, work[blockIdx.x], words, err, pmax, xs, red_lds, tmp, bcast, s_id, s_v, sA_lds);
 }
 
 // Every long segment of a launch in one cooperative launch of at most the co-resident
@@ -1029,17 +1031,17 @@ k_sweep_long_flat(const SweepArgs* __restrict__ tab, const LongWork* __restrict_
 // block; the blocks holding parts of earlier segments finish without waiting on later
 // parts, and each block takes a new ticket as soon as it is free, so every wait ends (given
 // B <= the grid, which the planner checks).  The list holds the largest B first.
-template <int E>
-__global__ void __launch_bounds__(kLongThreads, 2)
+template <int E, int NT, int BPC>
+__global__ void __launch_bounds__(NT, BPC)
 k_sweep_long_queue(const SweepArgs* __restrict__ tab, const LongWork* __restrict__ work, int nparts,
                    unsigned long long* __restrict__ words, unsigned long long* __restrict__ ticket,
                    unsigned* __restrict__ err, int pmax) {
     __shared__ float xs[NMFKL_R_MAX];
-    __shared__ float red_lds[2 * (kLongThreads / 64) * kMaxRed];
-    __shared__ double tmp[CoopReducer<kLongThreads>::J * kMaxRed];
+    __shared__ float red_lds[2 * (NT / 64) * kMaxRed];
+    __shared__ double tmp[CoopReducer<NT>::J * kMaxRed];
     __shared__ double bcast[kMaxRed];
-    __shared__ int32_t s_id[kLongThreads * E];
-    __shared__ float s_v[kLongThreads * E];
+    __shared__ int32_t s_id[NT * E];
+    __shared__ float s_v[NT * E];
     __shared__ double sA_lds[NMFKL_R_MAX];
     __shared__ int s_ticket;
     for (;;) {
@@ -1049,7 +1051,7 @@ k_sweep_long_queue(const SweepArgs* __restrict__ tab, const LongWork* __restrict
         const int t = __builtin_amdgcn_readfirstlane(s_ticket);
         __syncthreads();
         if (t >= nparts) break;
-        long_part<true, E>(tab, work[t], words, err, pmax, xs, red_lds, tmp, bcast, s_id, s_v, sA_lds);
+        long_part<true, E, NT>(tab, work[t], words, err, pmax, xs, red_lds, tmp, bcast, s_id, s_v, sA_lds);
     }
 }
 
@@ -1067,7 +1069,7 @@ hipError_t launch_sweep_long_single(const SweepArgs* tab, const LongWork* work, 
 
 hipError_t launch_sweep_long(const SweepArgs* tab, const LongWork* work, int nparts, int grid,
                              unsigned long long* words, int ngroups, unsigned* err, int pmax, bool cooperative,
-                             hipStream_t stream) {
+                             bool wide, hipStream_t stream) {
     if (nparts <= 0 || grid <= 0) return hipSuccess;
     // the groups' words, then the ticket counter
     const int64_t nwords = (int64_t)ngroups * 2 * pmax * kCoopValues;
@@ -1076,25 +1078,22 @@ hipError_t launch_sweep_long(const SweepArgs* tab, const LongWork* work, int npa
                        nwords + 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (grid == nparts) {
-        // every part has a block of its own
-        if (!cooperative) {
-            hipLaunchKernelGGL((k_sweep_long_flat<kCoopE>), dim3(grid), dim3(kLongThreads), 0, stream, tab, work,
-                               words, err, pmax);
-            return hipGetLastError();
-        }
-        void* fargs[] = {&tab, &work, &words, &err, &pmax};
-        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_sweep_long_flat<kCoopE>), dim3(grid),
-                                          dim3(kLongThreads), fargs, 0, stream);
-    }
-    if (!cooperative) {
-        hipLaunchKernelGGL((k_sweep_long_queue<kCoopE>), dim3(grid), dim3(kLongThreads), 0, stream, tab, work,
-                           nparts, words, ticket, err, pmax);
-        return hipGetLastError();
-    }
-    void* args[] = {&tab, &work, &nparts, &words, &ticket, &err, &pmax};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_sweep_long_queue<kCoopE>), dim3(grid),
-                                      dim3(kLongThreads), args, 0, stream);
+    // one part per block when every part has a block of its own, else the ticket queue; wide:
+    // blocks of kWideThreads (the parts were cut at kWideCapacity)
+    const bool flat = grid == nparts;
+    const void* fn;
+    if (wide)
+        fn = flat ? reinterpret_cast<const void*>(k_sweep_long_flat<kCoopE, kWideThreads, kWideBlocksPerCU>)
+                  : reinterpret_cast<const void*>(k_sweep_long_queue<kCoopE, kWideThreads, kWideBlocksPerCU>);
+    else
+        fn = flat ? reinterpret_cast<const void*>(k_sweep_long_flat<kCoopE, kCoopThreads, kCoopBlocksPerCU>)
+                  : reinterpret_cast<const void*>(k_sweep_long_queue<kCoopE, kCoopThreads, kCoopBlocksPerCU>);
+    const dim3 block(wide ? kWideThreads : kCoopThreads);
+    void* fargs[] = {&tab, &work, &words, &err, &pmax};
+    void* qargs[] = {&tab, &work, &nparts, &words, &ticket, &err, &pmax};
+    // cooperative = false (inside a captured graph): an ordinary launch of the same grid
+    if (cooperative) return hipLaunchCooperativeKernel(fn, dim3(grid), block, flat ? fargs : qargs, 0, stream);
+    return hipLaunchKernel(fn, dim3(grid), block, flat ? fargs : qargs, 0, stream);
 }
 
 int long_single_blocks_per_cu() {
@@ -1105,10 +1104,20 @@ int long_single_blocks_per_cu() {
     return nb;
 }
 
+int wide_kernel_blocks_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, reinterpret_cast<const void*>(k_sweep_long_queue<kCoopE, kWideThreads, kWideBlocksPerCU>), kWideThreads,
+            0) != hipSuccess)
+        return 0;
+    return nb;
+}
+
 int long_kernel_blocks_per_cu() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_sweep_long_queue<kCoopE>),
-                                                     kLongThreads, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(
+                                                              k_sweep_long_queue<kCoopE, kCoopThreads, kCoopBlocksPerCU>),
+                                                     kCoopThreads, 0) != hipSuccess)
         return 0;
     return nb;
 }

@@ -466,12 +466,13 @@ def test_huge_row_matches_the_oracle():
 def boundary_rows_problem(r=6, seed=0):
     """Rows whose lengths sit on both sides of every length boundary of the W-half's launches:
     the binned variants (32, 64, 96, 128, 192, 256, 384, 512, 768, 1024), the single-block kernel (2048), one
-    cooperative block (5120) and the queue bound (20 blocks = 102,400), plus 800 rows of
-    1025..2048 nonzeros (more than one wave of the single-block kernel on a 256-CU device)."""
+    cooperative block (5120), the queue bound (20 blocks = 102,400) and a whole number of the
+    wide blocks that the longer rows take (11 x 10,240), plus 800 rows of 1025..2048 nonzeros
+    (more than one wave of the single-block kernel on a 256-CU device)."""
     g = np.random.default_rng(seed)
-    edges = [32, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 2048, 5120, 20 * 5120]
+    edges = [32, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 2048, 5120, 20 * 5120, 11 * 10240]
     lengths = [L for e in edges for L in (e, e + 1)] + list(g.integers(1025, 2049, 800))
-    n, m = len(lengths), 20 * 5120 + 1
+    n, m = len(lengths), 11 * 10240 + 1
     rows = np.concatenate([np.full(L, i, np.int64) for i, L in enumerate(lengths)])
     cols = np.concatenate([g.choice(m, L, replace=False) for L in lengths])
     order = np.lexsort((rows, cols))
@@ -485,7 +486,7 @@ def boundary_rows_problem(r=6, seed=0):
 def test_every_length_boundary_matches_the_oracle():
     prob = boundary_rows_problem()
     lens = np.diff(prob.csr_ptr)
-    assert lens.max() == 20 * 5120 + 1 and ((lens > 1024) & (lens <= 2048)).sum() > 768
+    assert lens.max() == 11 * 10240 + 1 and ((lens > 1024) & (lens <= 2048)).sum() > 768
     t = 1
     ids = oracle.permutation(0, t, 0, prob.r)
     Wo, _, _ = oracle.sweep_W(prob, prob.F0.astype(np.float64), prob.W0.astype(np.float64), ids)
@@ -495,7 +496,7 @@ def test_every_length_boundary_matches_the_oracle():
     # each boundary row on its own (the 800 extra rows would hide one wrong row in the norm)
     err = np.linalg.norm(Wg - Wo, axis=1)
     norm = np.linalg.norm(Wo, axis=1)
-    nb = 26
+    nb = 28
     worst = float(np.max(err[:nb] / (norm[:nb] + 1e-5 * norm.max())))
     print(f"boundary rows: W rel {relf(Wg, Wo):.2e} (worst boundary row {worst:.2e}), F rel {relf(Fg, Fo):.2e}")
     assert relf(Wg, Wo) <= 1e-4 and relf(Fg, Fo) <= 1e-4
@@ -531,3 +532,31 @@ def test_queue_of_many_long_rows_matches_the_oracle():
     P.nmfkl_destroy(h)
     print(f"queue rows ({parts} parts): W rel {relf(Wg, W):.2e}, F rel {relf(Fg, F):.2e}")
     assert relf(Wg, W) <= 1e-4 and relf(Fg, F) <= 1e-4
+
+
+def test_queue_of_many_waves_matches_the_oracle():
+    """1,900 rows of 8,000-11,000 nonzeros: a queue of more than 8 waves of the co-resident
+    capacity, which runs on the wide blocks (512 threads, 10,240 nonzeros each).  Every row
+    is checked on its own."""
+    import torch
+    g = np.random.default_rng(5)
+    n, m, r = 1900, 24000, 4
+    lengths = g.integers(8000, 11001, n)
+    rows = np.concatenate([np.full(L, i, np.int64) for i, L in enumerate(lengths)])
+    cols = np.concatenate([g.choice(m, L, replace=False) for L in lengths])
+    order = np.lexsort((rows, cols))
+    rows, cols = rows[order], cols[order]
+    ptr = np.zeros(m + 1, np.int64)
+    np.cumsum(np.bincount(cols, minlength=m), out=ptr[1:])
+    val = g.geometric(0.6, rows.size).astype(np.float32)
+    prob = workloads._problem(n, m, r, ptr, rows.astype(np.int32), val, 5, 14, {"name": "many-wave queue"})
+    parts = int(np.sum((lengths + 5119) // 5120))
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    assert parts > 8 * 2 * ncu
+    t = 2
+    ids = oracle.permutation(0, t, 0, r)
+    Wo, _, _ = oracle.sweep_W(prob, prob.F0.astype(np.float64), prob.W0.astype(np.float64), ids)
+    Wg = gpu_half(prob, prob.W0, prob.F0, t, "W")
+    err = np.linalg.norm(Wg - Wo, axis=1) / (np.linalg.norm(Wo, axis=1) + 1e-5 * np.abs(Wo).max())
+    print(f"many-wave queue ({parts} parts of 5120): W rel {relf(Wg, Wo):.2e}, worst row {err.max():.2e}")
+    assert relf(Wg, Wo) <= 1e-4 and err.max() <= 1e-3
