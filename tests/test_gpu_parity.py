@@ -537,7 +537,8 @@ def test_queue_of_many_long_rows_matches_the_oracle():
 def test_queue_of_many_waves_matches_the_oracle():
     """1,900 rows of 8,000-11,000 nonzeros: a queue of more than 8 waves of the co-resident
     capacity, which runs on the wide blocks (512 threads, 10,240 nonzeros each).  Every row
-    is checked on its own."""
+    is checked on its own, and a second run gives the same factors bit for bit (partners'
+    sums are added in part order, whatever order the blocks arrive in)."""
     import torch
     g = np.random.default_rng(5)
     n, m, r = 1900, 24000, 4
@@ -560,3 +561,4 @@ def test_queue_of_many_waves_matches_the_oracle():
     err = np.linalg.norm(Wg - Wo, axis=1) / (np.linalg.norm(Wo, axis=1) + 1e-5 * np.abs(Wo).max())
     print(f"many-wave queue ({parts} parts of 5120): W rel {relf(Wg, Wo):.2e}, worst row {err.max():.2e}")
     assert relf(Wg, Wo) <= 1e-4 and err.max() <= 1e-3
+    assert np.array_equal(gpu_half(prob, prob.W0, prob.F0, t, "W"), Wg)
