@@ -23,12 +23,12 @@ struct BinPlan {
     int32_t* segs = nullptr;    // device
     int nblocks = 0;
     // long segments: those fitting one block in an ordinary launch (single_blocks entries at
-    // the start of long_work), the others in cooperative launches of at most the co-residency
-    // capacity: one per pack of segments of more than kQueueMaxB blocks (a block per part),
-    // then one queue launch for the rest (blocks take parts through a ticket counter)
+    // the start of long_work), the others in a cooperative launch of at most the co-residency
+    // capacity whose blocks take parts through a ticket counter (one part per block when all
+    // fit at once)
     LongWork* long_work = nullptr;  // device: single-block entries, then each launch's parts
     int single_blocks = 0;
-    // nblocks: parts; grid: blocks; wide: one part per block of kWideThreads
+    // nblocks: parts; grid: blocks; wide: blocks of kWideThreads (parts of kWideCapacity)
     struct Round { int first, nblocks, ngroups, pmax, grid; bool wide; };
     std::vector<Round> rounds;
     int max_groups = 0, max_pmax = 0;
@@ -263,21 +263,14 @@ void free_plan(BinPlan* p) {
 // Segments up to kMaxFusedLength: grouped by variant (longest variants first, so that long
 // blocks start early); inside a variant each problem's segments are sorted longest first and
 // cut into blocks of kFusedThreads / G segments of that problem, and the blocks of all
-// problems are ordered by their first segment, longest first.  Longer segments: B =
-// ceil(L / kLongCapacity) blocks each; those with B = 1 in one ordinary launch, the others in
-// cooperative launches: segments of more than kQueueMaxB blocks packed longest first, then
-// one launch that works through the rest as a queue, largest first (single-block segments
-// beyond the last full wave of the ordinary launch join the end of the queue).
-// Largest B that a segment of the cooperative queue may have.  In the queue the blocks that
-// take the first parts of a segment wait until its last part is taken; on the corpus (B <= 20)
-// the queue beats launches per pack of segments (long_W 1.28 vs 1.54 ms), on the large corpus
-// (B up to 387) the segments of more than 20 blocks run faster in packs (long_W 128 ms with
-// this bound, 131 ms with 32, 133 ms with everything queued; 12 costs the corpus 0.06 ms).
-constexpr int kQueueMaxB = 20;
+// problems are ordered by their first segment, longest first.  Longer segments: those that
+// fit one block of the single-block kernel in one ordinary launch, the others in one
+// cooperative launch that works through them as a queue, largest first (single-block
+// segments beyond the last full wave of the ordinary launch join the end of the queue).
 // A queue of more than this many waves of the co-resident capacity runs on the wide blocks:
 // on the corpus (3.5 waves) two blocks of 256 per unit are faster (long_W 1.32 ms against
 // 1.53 ms with wide blocks), on the large corpus (about 50 waves) the wide blocks are (long_W
-// 129 ms against 137 ms; wide blocks for the launches of the longest segments alone: 135 ms).
+// 125 ms against 137 ms in a measuring harness).
 constexpr int kWideQueueWaves = 8;
 
 int plan_bins(const std::vector<SegSource>& src, int long_capacity, int single_capacity, int wide_capacity,
@@ -374,16 +367,26 @@ int plan_bins(const std::vector<SegSource>& src, int long_capacity, int single_c
         std::stable_sort(single.begin(), single.end(), [](const LongSeg& a, const LongSeg& b) { return a.prob < b.prob; });
     for (const LongSeg& l : single) lw.push_back(LongWork{l.q, 0, 1, 0, l.prob, 0});
     plan->single_blocks = (int)lw.size();
-    // Segments of more than kQueueMaxB blocks run in launches of their own, each holding the
-    // next segments that fit (longest first): in the queue, the first blocks to take a part of
-    // such a segment would wait for many partners while the blocks ahead of them finish.
-    // These launches use the wide blocks (parts of kWideCapacity).  The rest share one queue
-    // launch.
+    // The rest (B >= 2, and single-block segments moved to the queue) share one cooperative
+    // launch that works through them as a queue, largest B first.  A queue of many waves runs
+    // on the wide blocks (parts of kWideCapacity: half as many partners per exchange, whose
+    // compute times spread when the chunk slices exceed the L2); a short queue keeps two
+    // narrow blocks per unit, whose exchanges overlap the other block's compute.  Both hold
+    // the same nonzeros per unit, so a segment that does not fit one fits neither.
     auto wide_blocks_of = [](const LongSeg& l) { return (int)((l.len + kWideCapacity - 1) / kWideCapacity); };
-    auto add_launch = [&](const std::vector<LongSeg>& list, bool as_queue, bool wide) {
+    if (!queued.empty()) {
+        int64_t parts = 0;
+        for (const LongSeg& l : queued) parts += blocks_of(l);
+        const bool wide = parts > (int64_t)kWideQueueWaves * long_capacity;
+        const int cap = wide ? wide_capacity : long_capacity;
         BinPlan::Round cur{(int)lw.size(), 0, 0, 0, 0, wide};
-        for (const LongSeg& l : list) {
+        for (const LongSeg& l : queued) {
             const int B = wide ? wide_blocks_of(l) : blocks_of(l);
+            if (B > cap) {
+                *err = "a segment of " + std::to_string(l.len) + " nonzeros needs " + std::to_string(B) +
+                       " co-resident blocks; this device holds " + std::to_string(cap);
+                return NMFKL_E_UNSUPPORTED;
+            }
             // B = 1 parts exchange nothing: they share group 0
             const int group = B > 1 ? cur.ngroups++ : 0;
             for (int p = 0; p < B; ++p) lw.push_back(LongWork{l.q, p, B, group, l.prob, 0});
@@ -391,41 +394,8 @@ int plan_bins(const std::vector<SegSource>& src, int long_capacity, int single_c
             cur.pmax = std::max(cur.pmax, B);
         }
         cur.ngroups = std::max(cur.ngroups, 1);
-        cur.grid = as_queue ? std::min(cur.nblocks, wide ? wide_capacity : long_capacity) : cur.nblocks;
+        cur.grid = std::min(cur.nblocks, cap);
         plan->rounds.push_back(cur);
-    };
-    std::vector<LongSeg> pack, rest;
-    int pack_blocks = 0;
-    for (const LongSeg& l : queued) {
-        const int B = blocks_of(l), Bw = wide_blocks_of(l);
-        if (B > kQueueMaxB && Bw > wide_capacity) {
-            *err = "a segment of " + std::to_string(l.len) + " nonzeros needs " + std::to_string(Bw) +
-                   " co-resident blocks; this device holds " + std::to_string(wide_capacity);
-            return NMFKL_E_UNSUPPORTED;
-        }
-        if (B > kQueueMaxB) {
-            if (pack_blocks + Bw > wide_capacity) {
-                add_launch(pack, false, true);
-                pack.clear();
-                pack_blocks = 0;
-            }
-            pack.push_back(l);
-            pack_blocks += Bw;
-        } else if (!pack.empty() && pack_blocks + Bw <= wide_capacity) {
-            pack.push_back(l);   // fills the last launch of large segments
-            pack_blocks += Bw;
-        } else {
-            rest.push_back(l);
-        }
-    }
-    if (!pack.empty()) add_launch(pack, false, true);
-    if (!rest.empty()) {
-        // a queue of many waves takes the wide blocks too (fewer partners per exchange, whose
-        // compute times spread when the chunk slices exceed the L2); a short one keeps two
-        // blocks per unit, whose exchanges overlap the other block's compute
-        int64_t parts = 0;
-        for (const LongSeg& l : rest) parts += blocks_of(l);
-        add_launch(rest, true, parts > (int64_t)kWideQueueWaves * long_capacity);
     }
     for (const auto& r : plan->rounds) {
         plan->max_groups = std::max(plan->max_groups, r.ngroups);

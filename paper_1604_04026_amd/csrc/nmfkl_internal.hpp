@@ -173,9 +173,8 @@ constexpr int kCoopThreads = 256;
 constexpr int kCoopBlocksPerCU = 2;
 constexpr int kCoopE = 20;
 constexpr int kCoopCapacity = kCoopThreads * kCoopE;
-// The launches of the longest segments (more than kQueueMaxB blocks of kCoopCapacity) use
-// blocks twice as wide, one per compute unit: the same nonzeros per unit, half as many
-// partners in each cross-block exchange.
+// A queue of many waves uses blocks twice as wide, one per compute unit: the same nonzeros
+// per unit, half as many partners in each cross-block exchange.
 constexpr int kWideThreads = 512;
 constexpr int kWideBlocksPerCU = 1;
 constexpr int kWideCapacity = kWideThreads * kCoopE;

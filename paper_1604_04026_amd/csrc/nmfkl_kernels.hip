@@ -1009,7 +1009,7 @@ k_sweep_long_single(const SweepArgs* __restrict__ tab, const LongWork* __restric
 }
 
 // Long segments whose parts all fit the co-resident capacity: one part per block of NT
-// threads (kCoopThreads, or kWideThreads for the launches of the longest segments).
+// threads (kCoopThreads, or kWideThreads).
 template <int E, int NT, int BPC>
 __global__ void __launch_bounds__(NT, BPC)
 k_sweep_long_flat(const SweepArgs* __restrict__ tab, const LongWork* __restrict__ work,
