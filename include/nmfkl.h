@@ -255,8 +255,8 @@ typedef struct nmfkl_batch_info {
     int32_t graph_cooperative;  /* 1: graphs hold cooperative launches; 0: ordinary launches of
                                    grids within the co-resident capacity; -1: no graph yet */
     int32_t fused_blocks[2];    /* blocks of the binned launch: F-half, W-half */
-    int32_t long_single_blocks[2];
-    int32_t long_rounds[2];     /* cooperative launches per half */
+    int32_t long_parts[2];      /* parts (blocks' worth of work) of the cooperative launch */
+    int32_t long_rounds[2];     /* cooperative launches per half (0 or 1) */
     int64_t nnz_total;
 } nmfkl_batch_info;
 

@@ -103,7 +103,7 @@ class NmfklTimings(ctypes.Structure):
 class NmfklBatchInfo(ctypes.Structure):
     _fields_ = [("nprob", ctypes.c_int32), ("bin_shift", ctypes.c_int32), ("tuning", ctypes.c_int32),
                 ("graph_cooperative", ctypes.c_int32), ("fused_blocks", ctypes.c_int32 * 2),
-                ("long_single_blocks", ctypes.c_int32 * 2), ("long_rounds", ctypes.c_int32 * 2),
+                ("long_parts", ctypes.c_int32 * 2), ("long_rounds", ctypes.c_int32 * 2),
                 ("nnz_total", ctypes.c_int64)]
 
     def as_dict(self):

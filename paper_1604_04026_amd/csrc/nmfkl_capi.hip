@@ -22,12 +22,9 @@ struct BinPlan {
     BlockWork* work = nullptr;  // device: blocks of the fused launch
     int32_t* segs = nullptr;    // device
     int nblocks = 0;
-    // long segments: those fitting one block in an ordinary launch (single_blocks entries at
-    // the start of long_work), the others in a cooperative launch of at most the co-residency
-    // capacity whose blocks take parts through a ticket counter (one part per block when all
-    // fit at once)
-    LongWork* long_work = nullptr;  // device: single-block entries, then each launch's parts
-    int single_blocks = 0;
+    // long segments: one cooperative launch of at most the co-residency capacity whose blocks
+    // take parts through a ticket counter (one part per block when all fit at once)
+    LongWork* long_work = nullptr;  // device: the launch's parts
     // nblocks: parts; grid: blocks; wide: blocks of kWideThreads (parts of kWideCapacity)
     struct Round { int first, nblocks, ngroups, pmax, grid; bool wide; };
     std::vector<Round> rounds;
@@ -80,7 +77,6 @@ struct nmfkl_handle {
     unsigned long long* coop_words = nullptr;  // tagged cross-block partial sums of long segments
     unsigned* dev_err = nullptr;       // device-side error flags (bounded waits), in dres's last word
     int long_capacity = 0;             // co-resident blocks of the cooperative long-segment kernel
-    int single_capacity = 0;           // co-resident blocks of the single-block long-segment kernel
     int wide_capacity = 0;             // co-resident blocks of its wide form
     BinPlan binF, binW;
     std::vector<int64_t> hptr_csc, hptr_csr;  // host copies of the segment pointers
@@ -238,20 +234,22 @@ void release(nmfkl_handle* h) {
     if (h->copy_stream) (void)hipStreamDestroy(h->copy_stream);
 }
 
-// Variant for a segment of length L in the fused launch (-1: too long).  bin_shift > 0 maps
-// a segment to the smallest variant holding L << bin_shift nonzeros (more lanes per nonzero;
-// the largest variant at most).
+// Variant for a segment of length L in the fused launch (-1: too long).  Segments of
+// 1025..2048 nonzeros take the last variant (256 x 8, LDS form).  bin_shift > 0 maps a shorter
+// segment to the smallest variant holding L << bin_shift nonzeros (more lanes per nonzero;
+// 256 x 4 at most).
 // pow2_only (tuning bit 2): only the variants of 4 and 8 nonzeros per lane, i.e. power-of-two
 // capacities (a segment that fits E = 3 or 6 gets the next variant of the same lane count,
 // whose extra elements stay empty: the same sums in the same order).
 int variant_for(int64_t L, int bin_shift, bool pow2_only = false) {
     if (L > kMaxFusedLength) return -1;
+    if (L > kMaxFusedLength / 2) return kNumVariants - 1;   // 256 x 8 (LDS form) for 1025..2048
     const int64_t Ls = L << bin_shift;
-    for (int v = 0; v < kNumVariants; ++v) {
+    for (int v = 0; v < kNumVariants - 1; ++v) {
         if (pow2_only && (kVariants[v].E & (kVariants[v].E - 1)) != 0) continue;
         if (Ls <= (int64_t)kVariants[v].G * kVariants[v].E) return v;
     }
-    return kNumVariants - 1;
+    return kNumVariants - 2;
 }
 
 void free_plan(BinPlan* p) {
@@ -263,17 +261,15 @@ void free_plan(BinPlan* p) {
 // Segments up to kMaxFusedLength: grouped by variant (longest variants first, so that long
 // blocks start early); inside a variant each problem's segments are sorted longest first and
 // cut into blocks of kFusedThreads / G segments of that problem, and the blocks of all
-// problems are ordered by their first segment, longest first.  Longer segments: those that
-// fit one block of the single-block kernel in one ordinary launch, the others in one
-// cooperative launch that works through them as a queue, largest first (single-block
-// segments beyond the last full wave of the ordinary launch join the end of the queue).
+// problems are ordered by their first segment, longest first.  Longer segments: one
+// cooperative launch that works through them as a queue, largest first.
 // A queue of more than this many waves of the co-resident capacity runs on the wide blocks:
 // on the corpus (3.5 waves) two blocks of 256 per unit are faster (long_W 1.32 ms against
 // 1.53 ms with wide blocks), on the large corpus (about 50 waves) the wide blocks are (long_W
 // 125 ms against 137 ms in a measuring harness).
 constexpr int kWideQueueWaves = 8;
 
-int plan_bins(const std::vector<SegSource>& src, int long_capacity, int single_capacity, int wide_capacity,
+int plan_bins(const std::vector<SegSource>& src, int long_capacity, int wide_capacity,
               int bin_shift, bool problem_major, BinPlan* plan, std::string* err, bool pow2_only = false) {
     struct LongSeg { int32_t q, prob; int64_t len; };
     const size_t ns = src.size();
@@ -346,30 +342,11 @@ int plan_bins(const std::vector<SegSource>& src, int long_capacity, int single_c
 
     std::stable_sort(longs.begin(), longs.end(), [](const LongSeg& a, const LongSeg& b) { return a.len > b.len; });
     std::vector<LongWork> lw;
-    // Segments of at most kLongCapacity nonzeros run one block each in an ordinary launch;
-    // longer ones take B = ceil(L / kCoopCapacity) co-resident blocks, largest B first.
     auto blocks_of = [](const LongSeg& l) { return (int)((l.len + kCoopCapacity - 1) / kCoopCapacity); };
-    std::vector<LongSeg> single, queued;
-    for (const LongSeg& l : longs) {
-        if (l.len <= kLongCapacity) single.push_back(l);
-        else queued.push_back(l);
-    }
-    // single-block segments that would start a last, partial wave of the single-block launch
-    // join the end of the queue instead (as B = 1)
-    if (!queued.empty() && single_capacity > 0 && (int)single.size() > single_capacity) {
-        const int over = (int)single.size() % single_capacity;
-        for (int k = 0; k < over; ++k) {
-            queued.push_back(single.back());
-            single.pop_back();
-        }
-    }
-    if (problem_major)
-        std::stable_sort(single.begin(), single.end(), [](const LongSeg& a, const LongSeg& b) { return a.prob < b.prob; });
-    for (const LongSeg& l : single) lw.push_back(LongWork{l.q, 0, 1, 0, l.prob, 0});
-    plan->single_blocks = (int)lw.size();
-    // The rest (B >= 2, and single-block segments moved to the queue) share one cooperative
-    // launch that works through them as a queue, largest B first.  A queue of many waves runs
-    // on the wide blocks (parts of kWideCapacity: half as many partners per exchange, whose
+    const std::vector<LongSeg>& queued = longs;
+    // Longer segments take B = ceil(L / kCoopCapacity) co-resident blocks each and share one
+    // cooperative launch that works through them as a queue, largest B first.  A queue of many
+    // waves runs on the wide blocks (parts of kWideCapacity: half as many partners per exchange, whose
     // compute times spread when the chunk slices exceed the L2); a short queue keeps two
     // narrow blocks per unit, whose exchanges overlap the other block's compute.  Both hold
     // the same nonzeros per unit, so a segment that does not fit one fits neither.
@@ -528,20 +505,19 @@ int refresh_model(nmfkl_handle* h) {
     return NMFKL_OK;
 }
 
-// Enqueues one half-sweep's sweep launches (long single-block, cooperative, fused)
+// Enqueues one half-sweep's sweep launches (cooperative long segments, then fused)
 // over the plan, with the argument table tab; timed: bracket them with the handle's timers.
 // stats: some entry of tab collects statistics.
 hipError_t enqueue_plan(const BinPlan& plan, const SweepArgs* tab, unsigned long long* coop_words,
                         unsigned* dev_err, bool cooperative, bool lookahead, bool stats, hipStream_t s,
                         nmfkl_handle* timed, int long_kind, int fused_kind, int open_timer = -1) {
     hipError_t e;
-    const bool any_long = plan.single_blocks > 0 || !plan.rounds.empty();
+    const bool any_long = !plan.rounds.empty();
     // timed groups follow each other: each one's start event ends the group before it
     // (open_timer: a group the caller started just before)
     int prev = open_timer;
     const int tl = (timed && any_long) ? timer_switch(timed, prev, long_kind) : -1;
     if (tl >= 0) prev = tl;
-    if ((e = launch_sweep_long_single(tab, plan.long_work, plan.single_blocks, s)) != hipSuccess) return e;
     for (const auto& rd : plan.rounds)
         if ((e = launch_sweep_long(tab, plan.long_work + rd.first, rd.nblocks, rd.grid, coop_words, rd.ngroups,
                                    dev_err, rd.pmax, cooperative, rd.wide, s)) != hipSuccess)
@@ -815,7 +791,6 @@ int create_ooc(const nmfkl_problem& pr, const nmfkl_params& prm, void* hip_strea
     int ncu = 0;
     OOC_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
     h->long_capacity = long_kernel_blocks_per_cu() * ncu;
-    h->single_capacity = long_single_blocks_per_cu() * ncu;
     h->wide_capacity = wide_kernel_blocks_per_cu() * ncu;
     if (h->long_capacity <= 0 || h->wide_capacity <= 0) {
         fail(h, NMFKL_E_DEVICE, "occupancy query of the long-segment kernel failed");
@@ -832,7 +807,7 @@ int create_ooc(const nmfkl_problem& pr, const nmfkl_params& prm, void* hip_strea
         for (auto& c : h->chunks[half]) {
             std::vector<int64_t> local(lptr.begin() + c.lptr, lptr.begin() + c.lptr + (c.seg1 - c.seg0) + 1);
             std::string why_plan;
-            const int rc = plan_bins({SegSource{&local, pr.r, 0}}, h->long_capacity, h->single_capacity, h->wide_capacity, prm.bin_shift, false, &c.plan,
+            const int rc = plan_bins({SegSource{&local, pr.r, 0}}, h->long_capacity, h->wide_capacity, prm.bin_shift, false, &c.plan,
                                      &why_plan, (prm.tuning & 4) != 0);
             if (rc) {
                 fail(h, rc, why_plan);
@@ -840,7 +815,7 @@ int create_ooc(const nmfkl_problem& pr, const nmfkl_params& prm, void* hip_strea
             }
             groups = std::max(groups, c.plan.max_groups);
             pmax = std::max(pmax, c.plan.max_pmax);
-            if (c.plan.single_blocks > 0 || !c.plan.rounds.empty()) h->long_half[half] = true;
+            if (!c.plan.rounds.empty()) h->long_half[half] = true;
         }
     if (h->long_half[0] || h->long_half[1]) OOC_HIP(dalloc(&h->Apc, (size_t)Pmax * ((pr.r + 3) & ~3)));
     OOC_HIP(dalloc(&h->coop_words, (size_t)groups * 2 * pmax * kCoopValues + 1));
@@ -991,7 +966,6 @@ int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_str
         int ncu = 0;
         CREATE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
         h->long_capacity = long_kernel_blocks_per_cu() * ncu;
-        h->single_capacity = long_single_blocks_per_cu() * ncu;
         h->wide_capacity = wide_kernel_blocks_per_cu() * ncu;
         if (h->long_capacity <= 0 || h->wide_capacity <= 0) {
             fail(h, NMFKL_E_DEVICE, "occupancy query of the long-segment kernel failed");
@@ -1002,17 +976,17 @@ int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_str
         CREATE_HIP(hipMemcpy(h->hptr_csc.data(), pr.csc_ptr, h->hptr_csc.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
         CREATE_HIP(hipMemcpy(h->hptr_csr.data(), pr.csr_ptr, h->hptr_csr.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
         std::string why_plan;
-        int rc = plan_bins({SegSource{&h->hptr_csc, pr.r, 0}}, h->long_capacity, h->single_capacity, h->wide_capacity, prm.bin_shift, false, &h->binF,
+        int rc = plan_bins({SegSource{&h->hptr_csc, pr.r, 0}}, h->long_capacity, h->wide_capacity, prm.bin_shift, false, &h->binF,
                            &why_plan, (prm.tuning & 4) != 0);
         if (!rc)
-            rc = plan_bins({SegSource{&h->hptr_csr, pr.r, 0}}, h->long_capacity, h->single_capacity, h->wide_capacity, prm.bin_shift, false, &h->binW,
+            rc = plan_bins({SegSource{&h->hptr_csr, pr.r, 0}}, h->long_capacity, h->wide_capacity, prm.bin_shift, false, &h->binW,
                            &why_plan, (prm.tuning & 4) != 0);
         if (rc) {
             fail(h, rc, why_plan);
             return bail(rc);
         }
-        h->long_half[0] = h->binF.single_blocks > 0 || !h->binF.rounds.empty();
-        h->long_half[1] = h->binW.single_blocks > 0 || !h->binW.rounds.empty();
+        h->long_half[0] = !h->binF.rounds.empty();
+        h->long_half[1] = !h->binW.rounds.empty();
         if (h->long_half[0] || h->long_half[1])
             CREATE_HIP(dalloc(&h->Apc, (size_t)Pmax * ((pr.r + 3) & ~3)));
         const int groups = std::max(h->binF.max_groups, h->binW.max_groups);
@@ -1228,7 +1202,6 @@ struct nmfkl_batch {
     unsigned* dev_err = nullptr;
     int64_t* t_dev = nullptr;
     int long_capacity = 0;
-    int single_capacity = 0;
     int wide_capacity = 0;
     int graph_coop = -1;
     std::vector<std::pair<int, hipGraphExec_t>> graphs;
@@ -1284,8 +1257,8 @@ int batch_plan(nmfkl_batch* b) {
     std::string why;
     const bool pm = (b->prm.tuning & 2) != 0;
     const bool p2 = (b->prm.tuning & 4) != 0;
-    int rc = plan_bins(srcF, b->long_capacity, b->single_capacity, b->wide_capacity, b->prm.bin_shift, pm, &b->plan[0], &why, p2);
-    if (!rc) rc = plan_bins(srcW, b->long_capacity, b->single_capacity, b->wide_capacity, b->prm.bin_shift, pm, &b->plan[1], &why, p2);
+    int rc = plan_bins(srcF, b->long_capacity, b->wide_capacity, b->prm.bin_shift, pm, &b->plan[0], &why, p2);
+    if (!rc) rc = plan_bins(srcW, b->long_capacity, b->wide_capacity, b->prm.bin_shift, pm, &b->plan[1], &why, p2);
     if (rc) return bfail(b, rc, why);
     const int groups = std::max(std::max(b->plan[0].max_groups, b->plan[1].max_groups), 1);
     const int pmax = std::max(std::max(b->plan[0].max_pmax, b->plan[1].max_pmax), 1);
@@ -1388,7 +1361,6 @@ int nmfkl_batch_create(int32_t nprob, const nmfkl_problem* probs, const nmfkl_pa
         b->hs.push_back(h);
     }
     b->long_capacity = b->hs[0]->long_capacity;
-    b->single_capacity = b->hs[0]->single_capacity;
     b->wide_capacity = b->hs[0]->wide_capacity;
     std::vector<SweepArgs> args(2 * (size_t)nprob);
     std::vector<PermJob> jobs(2 * (size_t)nprob);
@@ -1583,7 +1555,7 @@ int nmfkl_batch_get_info(nmfkl_batch* b, nmfkl_batch_info* out) {
     out->graph_cooperative = b->graph_coop;
     for (int half = 0; half < 2; ++half) {
         out->fused_blocks[half] = b->plan[half].nblocks;
-        out->long_single_blocks[half] = b->plan[half].single_blocks;
+        out->long_parts[half] = b->plan[half].rounds.empty() ? 0 : b->plan[half].rounds[0].nblocks;
         out->long_rounds[half] = (int32_t)b->plan[half].rounds.size();
     }
     for (nmfkl_handle* h : b->hs) out->nnz_total += h->prob.nnz;

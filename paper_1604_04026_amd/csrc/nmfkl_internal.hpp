@@ -155,20 +155,15 @@ struct BlockWork {
 
 // The (G lanes per segment, E elements per lane) variants of the fused launch.
 struct Variant { int G, E; };
-constexpr int kNumVariants = 10;
-constexpr Variant kVariants[kNumVariants] = {{8, 4},  {16, 4}, {32, 3}, {32, 4},  {64, 3},
-                                             {64, 4}, {64, 6}, {64, 8}, {256, 3}, {256, 4}};
+constexpr int kNumVariants = 11;
+constexpr Variant kVariants[kNumVariants] = {{8, 4},  {16, 4}, {32, 3},  {32, 4},  {64, 3}, {64, 4},
+                                             {64, 6}, {64, 8}, {256, 3}, {256, 4}, {256, 8}};
 constexpr int kFusedThreads = 256;
-constexpr int kMaxFusedLength = 1024;   // 256 * 4
+constexpr int kMaxFusedLength = 2048;   // 256 * 8 (the last variant, for 1025..2048 only)
 
-// Longer segments of at most kLongCapacity nonzeros: one block of kLongThreads threads with
-// kLongE nonzeros per thread.
-constexpr int kLongThreads = 256;
-constexpr int kLongE = 8;
-constexpr int kLongCapacity = kLongThreads * kLongE;
-// Segments longer than kLongCapacity: blocks of kCoopThreads threads x kCoopE nonzeros
-// (kCoopBlocksPerCU blocks per compute unit; more nonzeros per unit than three blocks of
-// kLongE), B = ceil(L / kCoopCapacity) of them per segment.
+// Segments longer than kMaxFusedLength: blocks of kCoopThreads threads x kCoopE nonzeros
+// (kCoopBlocksPerCU blocks per compute unit), B = ceil(L / kCoopCapacity) of them per
+// segment, cooperating through cross-block exchanges.
 constexpr int kCoopThreads = 256;
 constexpr int kCoopBlocksPerCU = 2;
 constexpr int kCoopE = 20;
@@ -202,9 +197,6 @@ hipError_t launch_model_terms(const double* M, const float* val, int64_t nnz, do
 // entry of the table collects statistics (the launch then keeps no counters).
 hipError_t launch_sweep_fused(const SweepArgs* tab, const BlockWork* work, const int32_t* segs,
                               int nblocks, bool lookahead, bool stats, hipStream_t stream);
-// Long segments that fit one block (B = 1): ordinary launch.
-hipError_t launch_sweep_long_single(const SweepArgs* tab, const LongWork* work, int nblocks,
-                                    hipStream_t stream);
 // Partial sums a cooperating block publishes per reduction (at most S1 and S2 of every
 // coordinate of an 8-wide chunk), one tagged 64-bit word each.
 constexpr int kCoopValues = 2 * kChunk;
@@ -222,8 +214,6 @@ hipError_t launch_sweep_long(const SweepArgs* tab, const LongWork* work, int npa
 int long_kernel_blocks_per_cu();
 // ... and of its wide form.
 int wide_kernel_blocks_per_cu();
-// ... and of the single-block long-segment kernel (0 on failure).
-int long_single_blocks_per_cu();
 hipError_t launch_model_objective(const int64_t* csc_ptr, const int32_t* csc_idx,
                                   const float* csc_val, int m, const float* W, const float* F, int r,
                                   double* Mcsc, double* partials, int nblocks, hipStream_t stream);

@@ -924,7 +924,8 @@ k_sweep_fused(const SweepArgs* __restrict__ tab, const BlockWork* __restrict__ w
         case 6: sweep_block_lds<64, 6, 4, STATS>(a, wk, segs, xs_all, sA_lds, s_id, s_v, red); break;
         case 7: sweep_block_lds<64, 8, 4, STATS>(a, wk, segs, xs_all, sA_lds, s_id, s_v, red); break;
         case 8: sweep_block<256, 3, LA256, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
-        default: sweep_block<256, 4, LA256, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
+        case 9: sweep_block<256, 4, LA256, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
+        default: sweep_block_lds<256, 8, 4, STATS>(a, wk, segs, xs_all, sA_lds, s_id, s_v, red); break;
     }
 }
 
@@ -943,21 +944,18 @@ hipError_t launch_sweep_fused(const SweepArgs* tab, const BlockWork* work, const
     return hipGetLastError();
 }
 
-// Long segments, lookahead form.  Segments of at most kLongCapacity nonzeros take one block
-// of kLongThreads threads x kLongE nonzeros (COOP = false, ordinary launch; 3 blocks per
-// compute unit within 168 registers).  Longer ones take B = ceil(L / kCoopCapacity) blocks of
-// kCoopThreads threads x kCoopE nonzeros (COOP = true: 256 x 20 at 2 blocks per compute unit,
-// 10240 nonzeros per unit, more than 3 blocks of 2048) that cooperate through CoopReducer; all blocks of
-// such a launch are co-resident (cooperative launch), so every wait ends.  Counts and ids
-// live in LDS, the model values in registers, w and u are recomputed from the model at each
-// chunk start, and tile chunks are 4 coordinates wide.
-constexpr int kLongCW = kChunkMajorW;
+// Long segments (more than kMaxFusedLength nonzeros), lookahead form: B = ceil(L /
+// kCoopCapacity) blocks of kCoopThreads threads x kCoopE nonzeros (256 x 20 at 2 blocks per
+// compute unit, 10240 nonzeros per unit; or the wide form, 512 x 20 at one block per unit)
+// cooperate through CoopReducer; all blocks of such a launch are co-resident (cooperative
+// launch), so every wait ends.  Counts and ids live in LDS, the model values in registers, w
+// and u are recomputed from the model at each chunk start, and tile chunks are 4 coordinates
+// wide.
 constexpr int kCoopCW = kChunkMajorW;
 
 // One block's part of a long segment (NT threads): the segment's x and column sums into LDS,
-// the sweep, and x back (part 0).  COOP: the blocks of the segment exchange through
-// CoopReducer.
-template <bool COOP, int E, int NT>
+// the sweep with the segment's other blocks (through CoopReducer), and x back (part 0).
+template <int E, int NT>
 __device__ __forceinline__ void long_part(const SweepArgs* __restrict__ tab, const LongWork& wk,
                                           unsigned long long* words, unsigned* err, int pmax, float* xs,
                                           float* red_lds, double* tmp, double* bcast, int32_t* s_id, float* s_v,
@@ -974,38 +972,20 @@ __device__ __forceinline__ void long_part(const SweepArgs* __restrict__ tab, con
     }
     a.sumA = sA_lds;
     __syncthreads();
-    if constexpr (COOP) {
-        CoopReducer<NT> red;
-        red.blk.red = red_lds;
-        red.blk.parity = 0;
-        red.tmp = tmp;
-        red.bcast = bcast;
-        red.words = words + (size_t)wk.group * 2 * pmax * kMaxRed;
-        red.err = err;
-        red.B = wk.B;
-        red.part = wk.part;
-        red.round = 0;
-        sweep_segment<NT, false, true, kCoopCW>(a, wk.seg, true, lane, wk.part * CAP,
-                                                          wk.part == 0, xs, red, st);
-    } else {
-        BlockReducer<NT> red{red_lds, 0, nullptr};
-        sweep_segment<NT, false, true, kLongCW>(a, wk.seg, true, lane, 0, true, xs, red, st);
-    }
+    CoopReducer<NT> red;
+    red.blk.red = red_lds;
+    red.blk.parity = 0;
+    red.tmp = tmp;
+    red.bcast = bcast;
+    red.words = words + (size_t)wk.group * 2 * pmax * kMaxRed;
+    red.err = err;
+    red.B = wk.B;
+    red.part = wk.part;
+    red.round = 0;
+    sweep_segment<NT, false, true, kCoopCW>(a, wk.seg, true, lane, wk.part * CAP, wk.part == 0, xs, red, st);
     __syncthreads();
     if (wk.part == 0)
         for (int s = lane; s < a.r; s += NT) a.X[(int64_t)wk.seg * a.r + a.ids[s]] = xs[s];
-}
-
-template <int E>
-__global__ void __launch_bounds__(kLongThreads, 3)
-k_sweep_long_single(const SweepArgs* __restrict__ tab, const LongWork* __restrict__ work) {
-    __shared__ float xs[NMFKL_R_MAX];
-    __shared__ float red_lds[2 * (kLongThreads / 64) * kMaxRed];
-    __shared__ int32_t s_id[kLongThreads * E];
-    __shared__ float s_v[kLongThreads * E];
-    __shared__ double sA_lds[NMFKL_R_MAX];
-    long_part<false, E, kLongThreads>(tab, work[blockIdx.x], nullptr, nullptr, 0, xs, red_lds, nullptr, nullptr, s_id, s_v,
-                        sA_lds);
 }
 
 // Long segments whose parts all fit the co-resident capacity: one part per block of NT
@@ -1021,7 +1001,7 @@ k_sweep_long_flat(const SweepArgs* __restrict__ tab, const LongWork* __restrict_
     __shared__ int32_t s_id[NT * E];
     __shared__ float s_v[NT * E];
     __shared__ double sA_lds[NMFKL_R_MAX];
-    long_part<true, E, NT>(tab, work[blockIdx.x], words, err, pmax, xs, red_lds, tmp, bcast, s_id, s_v, sA_lds);
+    long_part<E, NT>(tab, work[blockIdx.x], words, err, pmax, xs, red_lds, tmp, bcast, s_id, s_v, sA_lds);
 }
 
 // Every long segment of a launch in one cooperative launch of at most the co-resident
@@ -1051,20 +1031,13 @@ k_sweep_long_queue(const SweepArgs* __restrict__ tab, const LongWork* __restrict
         const int t = __builtin_amdgcn_readfirstlane(s_ticket);
         __syncthreads();
         if (t >= nparts) break;
-        long_part<true, E, NT>(tab, work[t], words, err, pmax, xs, red_lds, tmp, bcast, s_id, s_v, sA_lds);
+        long_part<E, NT>(tab, work[t], words, err, pmax, xs, red_lds, tmp, bcast, s_id, s_v, sA_lds);
     }
 }
 
 __global__ void k_zero_u64(unsigned long long* p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0ull;
-}
-
-hipError_t launch_sweep_long_single(const SweepArgs* tab, const LongWork* work, int nblocks,
-                                    hipStream_t stream) {
-    if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_sweep_long_single<kLongE>), dim3(nblocks), dim3(kLongThreads), 0, stream, tab, work);
-    return hipGetLastError();
 }
 
 hipError_t launch_sweep_long(const SweepArgs* tab, const LongWork* work, int nparts, int grid,
@@ -1094,14 +1067,6 @@ hipError_t launch_sweep_long(const SweepArgs* tab, const LongWork* work, int npa
     // cooperative = false (inside a captured graph): an ordinary launch of the same grid
     if (cooperative) return hipLaunchCooperativeKernel(fn, dim3(grid), block, flat ? fargs : qargs, 0, stream);
     return hipLaunchKernel(fn, dim3(grid), block, flat ? fargs : qargs, 0, stream);
-}
-
-int long_single_blocks_per_cu() {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(k_sweep_long_single<kLongE>),
-                                                     kLongThreads, 0) != hipSuccess)
-        return 0;
-    return nb;
 }
 
 int wide_kernel_blocks_per_cu() {

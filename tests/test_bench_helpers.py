@@ -25,12 +25,12 @@ def _write(path, counter, copy_kib, fused_kib, terms_kib, long_kib=(30.0, 20.0, 
         add("__amd_rocclr_copyBuffer", copy_kib)
     for sweep in range(4):               # each half: sums, long-segment launches, binned launch; then the terms
         add("nmfkl::k_permute_jobs(...)", 7.0)
-        add("void nmfkl::k_sweep_long_single<8>(...)", long_kib[0])
+        add("void nmfkl::k_sweep_long_flat<20, 256, 2>(...)", long_kib[0])
         add("void nmfkl::k_sweep_fused<false>(...)", fused_kib[0])
         add("nmfkl::k_permute_jobs(...)", 7.0)
-        add("void nmfkl::k_sweep_long_single<8>(...)", long_kib[1])
+        add("void nmfkl::k_sweep_long_flat<20, 256, 2>(...)", long_kib[1])
         add("nmfkl::k_zero_u64(...)", 1.0)
-        add("void nmfkl::k_sweep_long_queue<20>(...)", long_kib[2])
+        add("void nmfkl::k_sweep_long_queue<20, 512, 1>(...)", long_kib[2])
         add("void nmfkl::k_sweep_fused<false>(...)", fused_kib[1])
         add("nmfkl::k_permute_jobs(...)", 7.0)
         add("nmfkl::k_model_terms(...)", terms_kib)
@@ -71,10 +71,10 @@ def test_valu_summary_weights_dispatches_by_duration(tmp_path):
             rows.append({**{f: 0 for f in FIELDS}, "Dispatch_Id": d, "Kernel_Name": name, "Counter_Name": counter,
                          "Counter_Value": v, "Start_Timestamp": 1000 * d, "End_Timestamp": 1000 * d + dur})
     for sweep in range(3):
-        add("void nmfkl::k_sweep_long_single<8>(...)", 40.0, 90.0, 100)
+        add("void nmfkl::k_sweep_long_flat<20, 256, 2>(...)", 40.0, 90.0, 100)
         add("void nmfkl::k_sweep_fused<false>(...)", 70.0, 85.0, 1000)
-        add("void nmfkl::k_sweep_long_single<8>(...)", 50.0, 90.0, 100)
-        add("void nmfkl::k_sweep_long_queue<20>(...)", 30.0, 90.0, 300)
+        add("void nmfkl::k_sweep_long_flat<20, 256, 2>(...)", 50.0, 90.0, 100)
+        add("void nmfkl::k_sweep_long_queue<20, 512, 1>(...)", 30.0, 90.0, 300)
         add("void nmfkl::k_sweep_fused<false>(...)", 80.0, 80.0, 500)
         add("nmfkl::k_model_terms(...)", 60.0, 99.0, 50)
     with open(path / "run_counter_collection.csv", "w", newline="") as fh:

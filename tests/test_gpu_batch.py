@@ -65,7 +65,7 @@ def test_batch_equals_solo_bitwise_and_graph_replays(problems):
     info = P.nmfkl_batch_get_info(b)
     print("batch info", info)
     assert info["nprob"] == len(problems) and info["graph_cooperative"] in (0, 1)
-    assert info["long_rounds"][1] >= 1 and info["long_single_blocks"][1] >= 1
+    assert info["long_rounds"][1] == 1 and info["long_parts"][1] >= 2
     for q, p in enumerate(problems):
         W, F, Ds = solo(p, 0, 4, prm)
         Wb, Fb = devs[q].W.cpu().numpy(), devs[q].F.cpu().numpy()
