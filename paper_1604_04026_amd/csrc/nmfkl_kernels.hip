@@ -8,11 +8,12 @@
 // e < E, in registers: the count v_l, the model Ax_l (float64), w_l = v_l/(Ax_l+eps) and
 // u_l = w_l/(Ax_l+eps) (float32), so that eq. 6's sums are
 //     S1 = sum_l v_l A_lk/(Ax_l+eps) = sum_l A_lk w_l,   S2 = sum_l A_lk^2 u_l,
-// and streams the fixed-factor values of its nonzeros through registers one chunk of
-// kChunk coordinates at a time (two float4 loads per nonzero per chunk, next chunk
-// prefetched while the current one is processed).  S1 and S2 are all-reduced over the G
-// lanes with DPP row operations (and LDS for multi-wave segments), so every lane of a
-// segment takes the same Newton decisions.
+// and streams the fixed-factor values of its nonzeros through registers one chunk of CW
+// coordinates at a time (8 in the binned register variants, 4 in the LDS-form variants and
+// the long-segment kernels; the kernels are latency-bound at their occupancy, where a
+// prefetched second chunk would spill).  S1 and S2 are all-reduced over the G lanes with DPP
+// row operations (and LDS, or a cross-block exchange, for multi-wave segments), so every lane
+// of a segment takes the same Newton decisions.
 //
 // Precision: the derivative sums are float32 (all terms are positive).  The model values
 // are float64 because a coordinate step can remove most of a nonzero's model value (for
@@ -233,11 +234,12 @@ hipError_t launch_finalize_jobs(const PermJob* jobs, int njobs, int nsum, hipStr
 }
 
 // --------------------------------------------------------------- the sweep
-// Per-segment element state held in registers.
 // Per-nonzero state of a lane's E nonzeros: the model ax (float64, registers) and the
 // count v, w = v/(ax+eps), u = w/(ax+eps) and the point id, either in registers
-// (RegElems) or in LDS slots e*STRIDE + lane of the block (LdsElems, for the long-segment
-// kernel, whose register budget holds the tile and the model of more nonzeros that way).
+// (RegElems) or in LDS slots e*STRIDE + lane of the block (LdsElems: the fold-in's block
+// kernel; LdsElemsNoWU, below, without w and u: the LDS-form binned variants and the
+// long-segment kernels, whose register budget holds the tile and the model of more
+// nonzeros that way).
 template <int E>
 struct RegElems {
     static constexpr int kE = E;
