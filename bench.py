@@ -336,8 +336,8 @@ def traffic_run(args):
         P.nmfkl_objective_carried(h)
     tim = P.nmfkl_get_timings(h)
     P.nmfkl_destroy(h)
-    print(json.dumps({"sweeps": 1 + args.steps, "gather_bytes": {k: v["gather_bytes"] for k, v in tim.items()}}),
-          flush=True)
+    print(json.dumps({"sweeps": 1 + args.steps, "gather_bytes": {k: v["gather_bytes"] for k, v in tim.items()},
+                      "updates": {k: v["updates"] for k, v in tim.items()}}), flush=True)
 
 
 def _counter_rows(path):
@@ -405,6 +405,40 @@ def valu_summarize(valu_dir, out_path):
            "utilization": {g: v.get("VALUUtilization") for g, v in out_groups.items()},
            "command": "rocprofv3 --pmc VALUBusy VALUUtilization -d <dir> -o run --output-format csv -- "
                       "python3 bench.py --traffic-run --steps 3; python3 bench.py --valu-summarize <dir> profiles/valu.json"}
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def insts_summarize(insts_dir, run_log, out_path):
+    """SQ_INSTS_VALU and SQ_INSTS_SALU (wave instructions) of each launch group of a
+    --traffic-run, per launch (mean over the sweeps after the warm-up sweep), and VALU lane
+    slots per coordinate update: 64 x VALU wave instructions / (nonzeros x r).  run_log is the
+    traffic run's output, whose JSON line holds each group's updates per launch."""
+    rows = _counter_rows(insts_dir)
+    with open(run_log) as fh:
+        info = json.loads([ln for ln in fh.read().splitlines() if ln.startswith("{")][-1])
+    updates = info["updates"]
+    groups = {}
+    for counter in ("SQ_INSTS_VALU", "SQ_INSTS_SALU"):
+        vals = [(int(r["Dispatch_Id"]), r["Kernel_Name"], 0, float(r["Counter_Value"]))
+                for r in rows if r.get("Counter_Name") == counter]
+        for g, v in launch_groups(vals).items():
+            if v:
+                groups.setdefault(g, {})[counter.lower() + "_per_launch"] = sum(v) / len(v)
+    for g, d in groups.items():
+        u = updates.get(g) or 0.0
+        if u > 0 and "sq_insts_valu_per_launch" in d:
+            d["valu_lane_slots_per_update"] = round(64.0 * d["sq_insts_valu_per_launch"] / u, 2)
+        d["updates_per_launch"] = u
+    out = {"kernel_source_sha256_16": source_hash(),
+           "counter": "SQ_INSTS_VALU and SQ_INSTS_SALU (wave instructions) per launch group of bench.py --traffic-run "
+                      "--steps 3, mean over the sweeps after the warm-up sweep; lane slots per update = 64 x VALU "
+                      "instructions / (nonzeros x r)",
+           "groups": groups,
+           "command": "rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU -d <dir> -o run --output-format csv -- python3 "
+                      "bench.py --traffic-run --steps 3 > <log>; python3 bench.py --insts-summarize <dir> <log> "
+                      "profiles/insts.json"}
     with open(out_path, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out, indent=1))
@@ -634,6 +668,9 @@ def main():
         return
     if len(sys.argv) >= 2 and sys.argv[1] == "--valu-summarize":
         valu_summarize(sys.argv[2], sys.argv[3])
+        return
+    if len(sys.argv) >= 2 and sys.argv[1] == "--insts-summarize":
+        insts_summarize(sys.argv[2], sys.argv[3], sys.argv[4])
         return
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)

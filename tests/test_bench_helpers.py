@@ -88,3 +88,42 @@ def test_valu_summary_weights_dispatches_by_duration(tmp_path):
     assert v["groups"]["long_W"] == pytest.approx((50.0 * 100 + 30.0 * 300) / 400, abs=0.05)
     assert v["utilization"]["fused_W"] == pytest.approx(80.0)
     assert v["kernel_source_sha256_16"] == bench.source_hash()
+
+
+def test_insts_summary_per_update(tmp_path):
+    """VALU wave instructions per launch group (mean over the sweeps after the warm-up
+    sweep; a half's long launches add up) and lane slots per update = 64 x instructions over
+    the group's nonzeros x r, which come from the traffic run's JSON line."""
+    path = tmp_path / "i"
+    os.makedirs(path)
+    rows, d = [], 0
+
+    def add(name, valu, salu):
+        nonlocal d
+        d += 1
+        for counter, v in (("SQ_INSTS_VALU", valu), ("SQ_INSTS_SALU", salu)):
+            rows.append({**{f: 0 for f in FIELDS}, "Dispatch_Id": d, "Kernel_Name": name, "Counter_Name": counter,
+                         "Counter_Value": v})
+    for sweep in range(4):
+        scale = 9.0 if sweep == 0 else 1.0   # the warm-up sweep is left out
+        add("void nmfkl::k_sweep_fused<false>(...)", 1000.0 * scale, 10.0)
+        add("void nmfkl::k_sweep_long_flat<20, 256, 2>(...)", 300.0, 5.0)
+        add("void nmfkl::k_sweep_long_queue<20, 512, 1>(...)", 100.0, 5.0)
+        add("void nmfkl::k_sweep_fused<false>(...)", 500.0, 10.0)
+        add("nmfkl::k_model_terms(...)", 50.0, 1.0)
+    with open(path / "run_counter_collection.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=FIELDS)
+        w.writeheader()
+        w.writerows(rows)
+    log = tmp_path / "run.log"
+    log.write_text("[bench] noise\n" + json.dumps({"sweeps": 4, "updates": {"fused_F": 640.0, "fused_W": 320.0,
+                                                                          "long_W": 1280.0, "terms": 0.0}}) + "\n")
+    out = tmp_path / "insts.json"
+    bench.insts_summarize(str(path), str(log), str(out))
+    g = json.loads(out.read_text())["groups"]
+    assert g["fused_F"]["sq_insts_valu_per_launch"] == pytest.approx(1000.0)
+    assert g["fused_F"]["valu_lane_slots_per_update"] == pytest.approx(100.0)
+    assert g["fused_W"]["valu_lane_slots_per_update"] == pytest.approx(100.0)
+    assert g["long_W"]["sq_insts_valu_per_launch"] == pytest.approx(400.0)
+    assert g["long_W"]["valu_lane_slots_per_update"] == pytest.approx(20.0)
+    assert "valu_lane_slots_per_update" not in g["terms"]
