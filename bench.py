@@ -13,7 +13,8 @@ Prints one JSON line.  Besides the contract fields it carries:
                 average HIP-event duration, against the 8 TB/s HBM peak; traffic from the
                 committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary when it was taken on the
                 current kernel source, else null; valu_busy_pct likewise from the committed
-                VALUBusy summary;
+                VALUBusy summary, and each group's valu_slots_per_update (64 x SQ_INSTS_VALU per
+                coordinate update) from the committed instruction-count summary;
   cpu_baseline  the FP64 oracle timed on the host cores on a bounded sample (the first
                 sweeps of the same workload from the same initial factors);
   sweep_ms      median, min and max of the timed sweeps (HIP events between steps);
@@ -84,6 +85,19 @@ def valu_busy_for(group: str):
     if t.get("kernel_source_sha256_16") != source_hash():
         return None
     return t.get("groups", {}).get(group)
+
+
+def valu_slots_for(group: str):
+    """VALU lane slots per coordinate update of a launch group from the committed
+    SQ_INSTS_VALU summary, if it matches the source."""
+    try:
+        with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "insts.json")) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != source_hash():
+        return None
+    return t.get("groups", {}).get(group, {}).get("valu_lane_slots_per_update")
 
 
 def cpu_baseline(prob, seconds: float, keep=(), min_sweeps: int = 0):
@@ -785,7 +799,8 @@ def main():
                          "achieved_GBps": round(step_bytes / (step_ms * 1e-3) / 1e9, 1),
                          "frac": round(step_bytes / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
                 "groups": {g: {"frac": round(k["gather_GBps"] / HBM_PEAK_GBS, 4), "ms": k["ms_per_launch"],
-                               "valu_busy_pct": valu_busy_for(g)} for g, k in kernels.items()}}
+                               "valu_busy_pct": valu_busy_for(g), "valu_slots_per_update": valu_slots_for(g)}
+                           for g, k in kernels.items()}}
 
     out = {
         "metric": "nnz·r CD updates/sec per sweep",
