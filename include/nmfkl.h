@@ -86,7 +86,7 @@ typedef struct nmfkl_params {
     int32_t bin_shift;         /* mapping of segments of <= 1024 nonzeros to lanes (0..3, default 0):
                                   a segment of L nonzeros runs on the smallest lane group that holds
                                   L << bin_shift nonzeros (8 x 4, 16 x 4, 32 x 3 or 4, 64 x 3, 4, 6 or
-                                  8, 256 x 3 or 4).  Changes
+                                  8, 256 x 3 or 4; segments of 1025..2048 always take 256 x 8).  Changes
                                   the summation order of eq. 6's sums, hence results in the last
                                   bits; results are identical for identical bin_shift */
     int32_t tile_bf16;         /* 0 (default): the fixed factor of a half-sweep is read in float32;
@@ -137,11 +137,11 @@ typedef struct nmfkl_stats {
 
 /* Launch groups timed when params.collect_timings is set. */
 #define NMFKL_T_SUMS_F 0   /* F-half: order, permuted copy of W and its float64 column sums */
-#define NMFKL_T_FUSED_F 1  /* F-half: the binned launch over columns of <= 1024 nonzeros */
-#define NMFKL_T_LONG_F 2   /* F-half: cooperative launches over longer columns */
+#define NMFKL_T_FUSED_F 1  /* F-half: the binned launch over columns of <= 2048 nonzeros */
+#define NMFKL_T_LONG_F 2   /* F-half: the cooperative launch over longer columns */
 #define NMFKL_T_SUMS_W 3   /* W-half: order, permuted copy of F and its column sums */
-#define NMFKL_T_FUSED_W 4  /* W-half: the binned launch over rows of <= 1024 nonzeros */
-#define NMFKL_T_LONG_W 5   /* W-half: cooperative launches over longer rows */
+#define NMFKL_T_FUSED_W 4  /* W-half: the binned launch over rows of <= 2048 nonzeros */
+#define NMFKL_T_LONG_W 5   /* W-half: the cooperative launch over longer rows */
 #define NMFKL_T_MODEL 6    /* model values at the nonzeros from W and F (+ eq. 1 terms) */
 #define NMFKL_T_TERMS 7    /* eq. 1 terms from the carried model values (nmfkl_objective_carried) */
 #define NMFKL_NUM_TIMED 8
@@ -181,8 +181,9 @@ int nmfkl_permutation(uint64_t seed, uint64_t t, uint64_t stream, int32_t r, int
  * scratch buffers.  With params.out_of_core the structure and values are validated on the
  * host (the transpose by per-row counts and an order-independent checksum of the entries),
  * the bins are built per chunk and no maps or model values are allocated.  Errors:
- * NMFKL_E_INVAL (shape/structure/value), NMFKL_E_NOMEM, NMFKL_E_DEVICE.  On error *out is
- * NULL. */
+ * NMFKL_E_INVAL (shape/structure/value), NMFKL_E_NOMEM, NMFKL_E_DEVICE, NMFKL_E_UNSUPPORTED
+ * (a column or row of more nonzeros than the cooperative launch holds at once: 10,240 per
+ * compute unit, about 2.6M on a 256-unit device).  On error *out is NULL. */
 int nmfkl_create(const nmfkl_problem* prob, const nmfkl_params* p, void* hip_stream,
                  nmfkl_handle** out);
 
