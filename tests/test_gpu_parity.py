@@ -226,7 +226,8 @@ def test_power_of_two_bins_give_identical_results():
 
 
 def long_corpus(seed=0):
-    """Rows up to ~20k nonzeros: single-block (1025..4096) and multi-block long segments."""
+    """Rows up to ~20k nonzeros: the binned launch's 256 x 8 variant (1025..2048), one
+    cooperative block (2049..5120) and several."""
     n, m, r = 2000, 20000, 12
     ptr, idx, val = workloads.corpus(n, m, 80.0, 1.0, 2000, 1.1, 0.6, seed=seed, tag=8)
     return workloads._problem(n, m, r, ptr, idx, val, seed, 8, {"name": f"corpus {n}x{m} r={r}"})
@@ -465,10 +466,10 @@ def test_huge_row_matches_the_oracle():
 
 def boundary_rows_problem(r=6, seed=0):
     """Rows whose lengths sit on both sides of every length boundary of the W-half's launches:
-    the binned variants (32, 64, 96, 128, 192, 256, 384, 512, 768, 1024), the single-block kernel (2048), one
-    cooperative block (5120), the queue bound (20 blocks = 102,400) and a whole number of the
-    wide blocks that the longer rows take (11 x 10,240), plus 800 rows of 1025..2048 nonzeros
-    (more than one wave of the single-block kernel on a 256-CU device)."""
+    the binned variants (32, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 2048), one cooperative
+    block (5120), 20 blocks (102,400) and a whole number of the wide blocks (11 x 10,240), plus
+    800 rows of 1025..2048 nonzeros (the binned launch's 256 x 8 variant, more of them than a
+    256-CU device holds at once)."""
     g = np.random.default_rng(seed)
     edges = [32, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 2048, 5120, 20 * 5120, 11 * 10240]
     lengths = [L for e in edges for L in (e, e + 1)] + list(g.integers(1025, 2049, 800))
