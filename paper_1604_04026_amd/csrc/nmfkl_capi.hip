@@ -153,13 +153,16 @@ hipError_t dalloc(T** p, size_t count) {
 }
 
 // ---- timing helpers -------------------------------------------------------------------
+// The timing events only ever give elapsed times, so they skip the system-scope fence of an
+// ordinary event record (a cache writeback and invalidation between launch groups, which the
+// next group would pay for): 3.005 -> 2.986 ms per corpus iteration with timings on.
 hipError_t take_event(nmfkl_handle* h, hipEvent_t* ev) {
     if (!h->event_pool.empty()) {
         *ev = h->event_pool.back();
         h->event_pool.pop_back();
         return hipSuccess;
     }
-    return hipEventCreate(ev);
+    return hipEventCreateWithFlags(ev, hipEventDisableSystemFence);
 }
 
 // Starts a timed launch group; returns the index of the pending record or -1 when off.
