@@ -85,8 +85,9 @@ typedef struct nmfkl_params {
                                   and 6 between them */
     int32_t bin_shift;         /* mapping of segments of <= 1024 nonzeros to lanes (0..3, default 0):
                                   a segment of L nonzeros runs on the smallest lane group that holds
-                                  L << bin_shift nonzeros (8 x 4, 16 x 4, 32 x 3 or 4, 64 x 3, 4, 6 or
-                                  8, 256 x 3 or 4; segments of 1025..2048 always take 256 x 8).  Changes
+                                  L << bin_shift nonzeros (8 x 3 or 4, 16 x 3 or 4, 32 x 3 or 4, 64 x 3,
+                                  4, 6 or 8, 256 x 3 or 4; segments of 1025..2048 always take
+                                  256 x 8).  Changes
                                   the summation order of eq. 6's sums, hence results in the last
                                   bits; results are identical for identical bin_shift */
     int32_t tile_bf16;         /* 0 (default): the fixed factor of a half-sweep is read in float32;

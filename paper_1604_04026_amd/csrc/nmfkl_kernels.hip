@@ -917,16 +917,18 @@ k_sweep_fused(const SweepArgs* __restrict__ tab, const BlockWork* __restrict__ w
     // the variants of kVariants, in its order (E = 3 between the E = 4 ones: lanes hold a
     // segment more tightly, so fewer lanes idle in its per-coordinate work)
     switch (wk.variant) {
-        case 0: sweep_block<8, 4, false, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
-        case 1: sweep_block<16, 4, false, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
-        case 2: sweep_block<32, 3, false, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
-        case 3: sweep_block<32, 4, false, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
-        case 4: sweep_block<64, 3, false, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
-        case 5: sweep_block<64, 4, false, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
-        case 6: sweep_block_lds<64, 6, 4, STATS>(a, wk, segs, xs_all, sA_lds, s_id, s_v, red); break;
-        case 7: sweep_block_lds<64, 8, 4, STATS>(a, wk, segs, xs_all, sA_lds, s_id, s_v, red); break;
-        case 8: sweep_block<256, 3, LA256, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
-        case 9: sweep_block<256, 4, LA256, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
+        case 0: sweep_block<8, 3, false, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
+        case 1: sweep_block<8, 4, false, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
+        case 2: sweep_block<16, 3, false, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
+        case 3: sweep_block<16, 4, false, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
+        case 4: sweep_block<32, 3, false, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
+        case 5: sweep_block<32, 4, false, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
+        case 6: sweep_block<64, 3, false, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
+        case 7: sweep_block<64, 4, false, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
+        case 8: sweep_block_lds<64, 6, 4, STATS>(a, wk, segs, xs_all, sA_lds, s_id, s_v, red); break;
+        case 9: sweep_block_lds<64, 8, 4, STATS>(a, wk, segs, xs_all, sA_lds, s_id, s_v, red); break;
+        case 10: sweep_block<256, 3, LA256, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
+        case 11: sweep_block<256, 4, LA256, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
         default: sweep_block_lds<256, 8, 4, STATS>(a, wk, segs, xs_all, sA_lds, s_id, s_v, red); break;
     }
 }
