@@ -81,12 +81,12 @@ typedef struct nmfkl_params {
                                   (lookahead) derivative sums also for segments of 257..1024 nonzeros;
                                   bit 1 (batches): blocks ordered problem by problem rather than by
                                   segment length across problems; bit 2: only the lane groups of 4 and
-                                  8 nonzeros per lane (power-of-two bin capacities), not those of 3
-                                  and 6 between them */
+                                  8 nonzeros per lane (power-of-two bin capacities), not those of 3,
+                                  5 and 6 between them */
     int32_t bin_shift;         /* mapping of segments of <= 1024 nonzeros to lanes (0..3, default 0):
                                   a segment of L nonzeros runs on the smallest lane group that holds
                                   L << bin_shift nonzeros (8 x 3 or 4, 16 x 3 or 4, 32 x 3 or 4, 64 x 3,
-                                  4, 6 or 8, 256 x 3 or 4; segments of 1025..2048 always take
+                                  4, 5, 6 or 8, 256 x 3 or 4; segments of 1025..2048 always take
                                   256 x 8).  Changes
                                   the summation order of eq. 6's sums, hence results in the last
                                   bits; results are identical for identical bin_shift */

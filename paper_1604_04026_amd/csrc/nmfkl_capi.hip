@@ -242,7 +242,7 @@ void release(nmfkl_handle* h) {
 // segment to the smallest variant holding L << bin_shift nonzeros (more lanes per nonzero;
 // 256 x 4 at most).
 // pow2_only (tuning bit 2): only the variants of 4 and 8 nonzeros per lane, i.e. power-of-two
-// capacities (a segment that fits E = 3 or 6 gets the next variant of the same lane count,
+// capacities (a segment that fits E = 3, 5 or 6 gets the next variant of the same lane count,
 // whose extra elements stay empty: the same sums in the same order).
 int variant_for(int64_t L, int bin_shift, bool pow2_only = false) {
     if (L > kMaxFusedLength) return -1;

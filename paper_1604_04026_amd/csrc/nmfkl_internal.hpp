@@ -155,9 +155,9 @@ struct BlockWork {
 
 // The (G lanes per segment, E elements per lane) variants of the fused launch.
 struct Variant { int G, E; };
-constexpr int kNumVariants = 13;
+constexpr int kNumVariants = 14;
 constexpr Variant kVariants[kNumVariants] = {{8, 3}, {8, 4}, {16, 3}, {16, 4},  {32, 3}, {32, 4}, {64, 3},
-                                             {64, 4}, {64, 6}, {64, 8}, {256, 3}, {256, 4}, {256, 8}};
+                                             {64, 4}, {64, 5}, {64, 6}, {64, 8}, {256, 3}, {256, 4}, {256, 8}};
 constexpr int kFusedThreads = 256;
 constexpr int kMaxFusedLength = 2048;   // 256 * 8 (the last variant, for 1025..2048 only)
 

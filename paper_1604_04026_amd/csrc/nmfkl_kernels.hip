@@ -925,10 +925,11 @@ k_sweep_fused(const SweepArgs* __restrict__ tab, const BlockWork* __restrict__ w
         case 5: sweep_block<32, 4, false, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
         case 6: sweep_block<64, 3, false, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
         case 7: sweep_block<64, 4, false, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
-        case 8: sweep_block_lds<64, 6, 4, STATS>(a, wk, segs, xs_all, sA_lds, s_id, s_v, red); break;
-        case 9: sweep_block_lds<64, 8, 4, STATS>(a, wk, segs, xs_all, sA_lds, s_id, s_v, red); break;
-        case 10: sweep_block<256, 3, LA256, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
-        case 11: sweep_block<256, 4, LA256, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
+        case 8: sweep_block<64, 5, false, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
+        case 9: sweep_block_lds<64, 6, 4, STATS>(a, wk, segs, xs_all, sA_lds, s_id, s_v, red); break;
+        case 10: sweep_block_lds<64, 8, 4, STATS>(a, wk, segs, xs_all, sA_lds, s_id, s_v, red); break;
+        case 11: sweep_block<256, 3, LA256, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
+        case 12: sweep_block<256, 4, LA256, kFusedCW, STATS>(a, wk, segs, xs_all, red, sA_lds); break;
         default: sweep_block_lds<256, 8, 4, STATS>(a, wk, segs, xs_all, sA_lds, s_id, s_v, red); break;
     }
 }
