@@ -209,7 +209,7 @@ def test_stats_counters():
 
 
 def test_power_of_two_bins_give_identical_results():
-    """tuning bit 2 maps segments that fit 3 or 6 nonzeros per lane to the 4- or 8-per-lane
+    """tuning bit 2 maps segments that fit 3, 5 or 6 nonzeros per lane to the 4- or 8-per-lane
     group of the same lane count: the extra elements stay empty, so both halves' factors are
     bit for bit those of the default bins."""
     prob = CASES["corpus_mid"]()
