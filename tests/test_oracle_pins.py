@@ -471,3 +471,25 @@ def test_r1_regularised_closed_form_W_half(orc):
     expect = (-(S + b) + np.sqrt((S + b) ** 2 + 4 * a * R)) / (2 * a)
     assert np.allclose(W2[:, 0], expect, rtol=1e-12, atol=1e-15)
     assert np.allclose(sf, F.sum(axis=0), rtol=1e-14)
+
+
+def test_checkpoint_and_resume_is_exact(orc):
+    """Alg. 1's state between outer iterations is (W, F, t): the coordinate order of
+    iteration t depends only on (seed, t), and every column and row starts from its model
+    values recomputed from the factors.  So 2 iterations, a checkpoint of W and F, and 2 more
+    iterations from t = 2 give the 4-iteration run bit for bit, with any thread count."""
+    prob = workloads.config(0, seed=5)
+    W4, F4, D4 = orc.run(prob, 4)
+    W2, F2, D2 = orc.run(prob, 2)
+    saved = (W2.copy(), F2.copy())
+    old = orc.threads()
+    try:
+        orc.set_threads(1)
+        Wr, Fr, Dr = orc.run(prob, 2, W=saved[0], F=saved[1], t0=2)
+    finally:
+        orc.set_threads(old)
+    assert np.array_equal(Wr, W4) and np.array_equal(Fr, F4)
+    assert np.array_equal(np.concatenate([D2, Dr]), D4)
+    # a resume with the wrong t is a different run
+    Wx, _, _ = orc.run(prob, 2, W=saved[0], F=saved[1], t0=3)
+    assert not np.array_equal(Wx, W4)
