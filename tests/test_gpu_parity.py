@@ -102,6 +102,35 @@ def test_trajectory_parity(case):
     assert relf(Wg, Wo) <= 1e-4 and relf(Fg, Fo) <= 1e-4
 
 
+def test_checkpoint_and_resume():
+    """A handle destroyed after 3 iterations and a new one created from the saved W and F
+    continue at t = 3: the new handle computes the model values from the factors, where the
+    continuous one carries them, so the two runs agree to float64 rounding of the model (far
+    inside the oracle tolerance), and the resumed run matches the oracle's 6 iterations."""
+    prob = CASES["corpus_mid"]()
+    dev = P.upload(prob, "cuda")
+    h = P.nmfkl_create(dev)
+    for t in range(6):
+        P.nmfkl_sweep_F(h, t)
+        P.nmfkl_sweep_W(h, t)
+        if t == 2:
+            saved = (dev.W.cpu().numpy(), dev.F.cpu().numpy())
+    Wc, Fc, Dc = dev.W.cpu().numpy(), dev.F.cpu().numpy(), P.nmfkl_objective(h)
+    P.nmfkl_destroy(h)
+    dev = P.upload(prob, "cuda", W=saved[0], F=saved[1])
+    h = P.nmfkl_create(dev)
+    for t in range(3, 6):
+        P.nmfkl_sweep_F(h, t)
+        P.nmfkl_sweep_W(h, t)
+    Wr, Fr, Dr = dev.W.cpu().numpy(), dev.F.cpu().numpy(), P.nmfkl_objective(h)
+    P.nmfkl_destroy(h)
+    Wo, Fo, Do = oracle.run(prob, 6)
+    print(f"resume vs continuous: W {relf(Wr, Wc):.2e} F {relf(Fr, Fc):.2e} D {abs(Dr - Dc) / Dc:.2e}; "
+          f"resume vs oracle: W {relf(Wr, Wo):.2e} F {relf(Fr, Fo):.2e} D {abs(Dr - Do[-1]) / Do[-1]:.2e}")
+    assert abs(Dr - Dc) <= 1e-7 * Dc and relf(Wr, Wc) <= 1e-5 and relf(Fr, Fc) <= 1e-5
+    assert abs(Dr - Do[-1]) <= 1e-5 * Do[-1] and relf(Wr, Wo) <= 1e-4 and relf(Fr, Fo) <= 1e-4
+
+
 def test_objective_parity():
     prob = CASES["corpus_mid"]()
     rng = np.random.default_rng(3)
